@@ -1,0 +1,17 @@
+"""Seeded synthetic inputs for the X-engine: quantised Gaussian voltages.
+
+This package only draws samples and encodes them in the input byte formats
+(4+4-bit packed, or 8+8-bit interleaved). It holds none of the correlation
+arithmetic, so both the CPU oracle's tests and the GPU path can take their
+inputs from it without sharing any of the method.
+"""
+from .gen import (  # noqa: F401
+    SEED_BASE,
+    draw_stream,
+    pack4,
+    pack8,
+    tone_channels,
+    tone_series,
+    workload,
+    WORKLOADS,
+)
