@@ -1,0 +1,159 @@
+"""X-engine benchmark: one JSON line on stdout.
+
+A step is one pass of the whole hot path over one gulp already resident in
+HBM: xeng_correlate (unpack, triangle schedule, int8-MFMA cross-multiply,
+integration into the int32 accumulator) followed by xeng_dump (device copy of
+the packed lower triangle and reset). The workload is the LEDA-shaped gulp:
+N = 512 inputs, 128 channels, 8192 samples of 4+4-bit quantised Gaussian
+voltages (sigma 2.5) with a common tone in 4 channels.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("complex MACs/s (Tops/s) at N=512, % int8 MFMA peak; real-time factor; "
+          "p99 gulp ms")
+OPS_PER_CMAC = 8                 # 4 real multiply-adds = 8 int8 ops
+PEAK_INT8_OPS = 5.0e15           # MI355X dense int8 MFMA, ops/s
+CHANNEL_HZ = 24.0e3              # channel width of the paper's F-engine (Section 2)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(samples, n_inputs, n_chans, n_time, budget_s=15.0):
+    """Time the CPU oracle on a bounded sample of the same gulp (whole channels)."""
+    import numpy as np
+
+    import oracle
+    oracle.build(force=False)
+    tri = n_inputs * (n_inputs + 1) // 2
+    cores = oracle.num_threads()
+    # calibrate on one channel, then size the sample to about budget_s seconds
+    t0 = time.perf_counter()
+    oracle.correlate(samples, 4, chans=[0])
+    one = time.perf_counter() - t0
+    n_sel = int(max(1, min(n_chans, round(budget_s / max(one, 1e-3) * cores / 2))))
+    n_sel = max(cores, (n_sel // cores) * cores) if n_sel >= cores else n_sel
+    n_sel = min(n_sel, n_chans)
+    chans = np.linspace(0, n_chans - 1, n_sel).round().astype(int).tolist()
+    t0 = time.perf_counter()
+    oracle.correlate(samples, 4, chans=chans)
+    dt = time.perf_counter() - t0
+    cmac = n_sel * tri * n_time
+    return {"value": cmac * OPS_PER_CMAC / dt / 1e12, "unit": "Tops/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "%d of %d channels of the same gulp (N=%d, T=%d), %.1f s" % (
+                n_sel, n_chans, n_inputs, n_time, dt),
+            "cmac_per_s": cmac / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU; this build has no multi-GPU path (--gpus %d "
+              "requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_1411_3751_amd import Correlator
+
+    torch.cuda.set_device(0)
+    name = "leda_gulp"
+    log("generating workload %s ..." % name)
+    samples, _, _, meta = synth.workload(name)
+    N, F, T = meta["n_inputs"], meta["n_chans"], meta["n_time"]
+    tri = N * (N + 1) // 2
+    cmac_per_step = F * tri * T
+    d_samples = torch.from_numpy(samples).cuda()
+    out = torch.empty((F, tri, 2), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    corr = Correlator([dict(n_inputs=N, n_chans=F, n_time=T, in_bits=4)], stream=stream)
+    log("plan:", json.dumps(corr.plan()))
+
+    def step():
+        corr.correlate([d_samples])
+        corr.dump([out], reset=True)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # whole steps
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for _ in range(args.steps):
+        step()
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ms_step = t_start.elapsed_time(t_end) / args.steps
+
+    # the dominant kernel alone: one correlate call = one launch of the tile kernel
+    k_start = torch.cuda.Event(enable_timing=True)
+    k_end = torch.cuda.Event(enable_timing=True)
+    corr.reset()
+    torch.cuda.synchronize()
+    k_start.record(stream)
+    for _ in range(args.steps):
+        corr.correlate([d_samples])
+        if corr.samples_since_dump() + T > corr.max_dump_samples():
+            corr.reset()
+    k_end.record(stream)
+    torch.cuda.synchronize()
+    ms_kernel = k_start.elapsed_time(k_end) / args.steps
+    corr.close()
+
+    ops_step = cmac_per_step * OPS_PER_CMAC
+    value = ops_step / (ms_step * 1e-3) / 1e12
+    achieved = ops_step / (ms_kernel * 1e-3) / 1e12
+    peak = PEAK_INT8_OPS / 1e12
+    stream_s = T / CHANNEL_HZ
+    res = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Tops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": "leda_gulp", "n_inputs": N, "n_chans": F, "n_time": T,
+                   "in_bits": 4, "engine": "i8"},
+        "cmac_per_s": cmac_per_step / (ms_step * 1e-3),
+        "pct_int8_peak": round(100.0 * value / peak, 2),
+        "rtf_gulp": round(stream_s / (ms_step * 1e-3), 1),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None},
+    }
+    if not args.no_cpu:
+        log("timing the CPU oracle on a sample ...")
+        res["cpu_baseline"] = cpu_baseline(samples, N, F, T)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

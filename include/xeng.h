@@ -1,0 +1,140 @@
+/*
+ * xeng.h - C ABI of the MI355X X-engine library (libxeng.so).
+ *
+ * The X-engine is the O(N^2) stage of an FX correlator (Section 1; Section
+ * 2.5; Fig. 2 caption: the X-engines cross-multiply and time-average the
+ * channelised voltages of every antenna pair). For every channel f and every
+ * pair of inputs i >= j it accumulates
+ *
+ *     V[f][i][j] = sum_t x_i(t, f) * conj(x_j(t, f))
+ *     Re V = sum_t (xr_i xr_j + xi_i xi_j),  Im V = sum_t (xi_i xr_j - xr_i xi_j)
+ *
+ * exactly, in integers, over the samples of successive xeng_correlate calls
+ * (Section 2.5: groups of spectra are cross-multiplied and summed to the dump
+ * cadence) until xeng_dump hands the sums out (Section 2.6: the accumulator
+ * is read out and zeroed). Sums are returned as sums; dividing by the sample
+ * count ("averaging") is left to the caller.
+ *
+ * Input samples (caller-owned DEVICE memory, layout [time][channel][input],
+ * i.e. after the corner turn of Fig. 2):
+ *   in_bits = 4 : one byte per complex sample, the F-engine's 4+4-bit output
+ *                 (Section 2.2). Real part in bits 7..4, imaginary part in
+ *                 bits 3..0, each two's complement in [-8, 7]; -8 is legal.
+ *   in_bits = 8 : two bytes per complex sample, int8 real then int8
+ *                 imaginary (the 8+8-bit form of Section 2.4), [-128, 127].
+ *
+ * Output (per subarray): int32 [n_chans][N(N+1)/2][2], the lower triangle
+ * i >= j including the autocorrelations, packed row by row at index
+ * i(i+1)/2 + j, each entry (re, im). Products XX, YY, XY, YX of dual-
+ * polarisation antennas (Table 1, note a) are entries of this matrix when
+ * input i = 2 * antenna + polarisation.
+ *
+ * Exactness: every result is the exact integer sum. The library refuses
+ * (XENG_ERANGE, before launching anything) a call that would let any sum
+ * leave int32: at most XENG_MAX_DUMP_SAMPLES_4BIT samples per dump for 4-bit
+ * input, XENG_MAX_DUMP_SAMPLES_8BIT for 8-bit input. The FP8 engine keeps
+ * every float partial sum below 2^24, so it additionally limits one call to
+ * XENG_MAX_CALL_SAMPLES_FP8 samples.
+ *
+ * Streams and ownership: xeng_correlate and xeng_dump enqueue work on the
+ * context's HIP stream and return; the caller keeps the sample buffers valid
+ * until that work has run. The library owns the accumulators; the caller owns
+ * sample and output buffers. A context is used from one host thread at a time.
+ *
+ * Every function returns 0 (XENG_OK) or a positive XENG_E* code; the detail
+ * of the last failure on the calling thread is in xeng_last_error().
+ */
+#ifndef XENG_H
+#define XENG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define XENG_OK 0
+#define XENG_EINVAL 1 /* bad argument: null pointer, size or option out of range */
+#define XENG_ERANGE 2 /* the call would break the exactness bound; nothing launched */
+#define XENG_ENOMEM 3 /* device allocation failed */
+#define XENG_EHIP 4   /* a HIP runtime call failed; see xeng_last_error() */
+
+#define XENG_ENGINE_I8 0  /* int8 MFMA, int32 accumulation */
+#define XENG_ENGINE_FP8 1 /* FP8 (OCP e4m3) MFMA, fp32 accumulation; in_bits == 4 only */
+
+#define XENG_MAX_DUMP_SAMPLES_4BIT 16777215LL /* floor((2^31 - 1) / 128) */
+#define XENG_MAX_DUMP_SAMPLES_8BIT 65535LL    /* floor((2^31 - 1) / 32768) */
+#define XENG_MAX_CALL_SAMPLES_FP8 32768LL     /* keeps fp32 partial sums < 2^24 */
+
+typedef struct xeng_ctx xeng_ctx; /* opaque, library-owned */
+
+/* One subarray: an independent set of inputs correlated with its own shape. */
+typedef struct {
+    int32_t n_inputs; /* N >= 1 inputs (input i = 2 * antenna + polarisation) */
+    int32_t n_chans;  /* F >= 1 channels */
+    int32_t n_time;   /* T >= 1 time samples consumed per xeng_correlate call */
+    int32_t in_bits;  /* 4 or 8, see above */
+    int32_t engine;   /* XENG_ENGINE_I8 or XENG_ENGINE_FP8 */
+} xeng_subarray;
+
+/*
+ * Create a context for n_subs (1..64) subarrays. Allocates the device
+ * accumulators (n_chans * N(N+1)/2 * 8 bytes each) on the current HIP device
+ * and plans the launches. hip_stream is a hipStream_t (NULL = the null
+ * stream). On success *out receives the context; on failure *out is NULL and
+ * nothing stays allocated. Errors: XENG_EINVAL (bad shape, engine/in_bits
+ * combination, n_time above the per-call limit of the engine), XENG_ENOMEM,
+ * XENG_EHIP.
+ */
+int xeng_create(const xeng_subarray *subs, int n_subs, void *hip_stream, xeng_ctx **out);
+
+/*
+ * Accumulate one call's samples of every subarray. d_samples[s] is a device
+ * pointer to subarray s's n_time x n_chans x n_inputs samples in the layout of
+ * its in_bits. Checks all bounds before launching anything: XENG_ERANGE if
+ * any subarray's samples since the last dump would exceed its dump limit,
+ * XENG_EINVAL for a null context or pointer. Enqueues on the context stream.
+ */
+int xeng_correlate(xeng_ctx *ctx, const void *const *d_samples);
+
+/*
+ * Copy every subarray's sums into out[s] (int32 [n_chans][N(N+1)/2][2]).
+ * out_is_device != 0: out[s] are device pointers, the copy is enqueued on the
+ * context stream and the call returns at once. out_is_device == 0: out[s] are
+ * host pointers; the call waits for the stream to finish the copy. reset != 0
+ * starts a new integration (the sums restart from zero and the sample count
+ * from 0) after the copy. out may be NULL when reset != 0 to discard the sums.
+ */
+int xeng_dump(xeng_ctx *ctx, void *const *out, int out_is_device, int reset);
+
+/* Release the context and its device memory (waits for its stream). NULL is a no-op. */
+int xeng_destroy(xeng_ctx *ctx);
+
+/* Point the context at another HIP stream (NULL = null stream) for later calls. */
+int xeng_set_stream(xeng_ctx *ctx, void *hip_stream);
+
+/* Samples accumulated into subarray sub since its last reset. */
+int xeng_samples_since_dump(const xeng_ctx *ctx, int sub, int64_t *out);
+
+/* Largest number of samples subarray sub may accumulate between dumps. */
+int xeng_max_dump_samples(const xeng_ctx *ctx, int sub, int64_t *out);
+
+/*
+ * Describe the launch plan (tile sizes, launch counts per call) as a
+ * NUL-terminated JSON object in buf (at most len bytes). XENG_EINVAL if buf
+ * is too small.
+ */
+int xeng_plan_describe(const xeng_ctx *ctx, char *buf, size_t len);
+
+/* Static text for an XENG_* code. */
+const char *xeng_strerror(int code);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *xeng_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XENG_H */

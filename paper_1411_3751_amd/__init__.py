@@ -1,0 +1,14 @@
+"""MI355X-native X-engine: exact int8/FP8-MFMA correlation of 4+4-bit voltages.
+
+The hot path is the HIP library ``libxeng.so`` (C ABI in ``include/xeng.h``);
+this package is its thin Python binding.
+"""
+from .xeng import (  # noqa: F401
+    ENGINE_FP8,
+    ENGINE_I8,
+    Correlator,
+    Subarray,
+    XengError,
+    load,
+    tri,
+)

@@ -1,0 +1,346 @@
+// X-engine tile kernel: int8 MFMA, int32 accumulation, gfx950 (CDNA4).
+//
+// One workgroup computes one (channel, I-block, J-block) tile of the lower
+// triangle of V[f] = sum_t x(t, f) x(t, f)^H (Section 2.5; Fig. 2 caption),
+// with J-block <= I-block, for the samples of one time segment.
+//
+// Data flow per stage of TK = 64 time samples:
+//   1. every thread loads 16 time rows x 4 inputs (one dword per row) of the
+//      [T][F][N] stream: each wave instruction reads 256 contiguous bytes;
+//   2. a 4x4 byte transpose in registers (v_perm) turns them into 4 inputs x
+//      16 consecutive time samples, written to LDS as packed rows
+//      [row][time] (1 byte per complex sample), double-buffered;
+//   3. each wave reads its 16-byte fragments (one input row, 16 samples) and
+//      unpacks them with masks only:
+//        w & 0xF0F0F0F0        = 16 * re   (high nibble, sign already in bit 7)
+//        (w << 4) & 0xF0F0F0F0 = 16 * im
+//        16*im ^ 0xF0F0F0F0    = 16 * (~im) = 16 * (-im - 1)
+//      (the negated operand uses ~im, not -im: -(-8 * 16) would leave int8);
+//   4. four v_mfma_i32_16x16x64_i8 per 16x16 sub-tile and stage:
+//        accR += (16re_i)(16re_j) + (16im_i)(16im_j)             = 256 Re V
+//        accI += (16re_i)(16(~im_j)) + (16im_i)(16re_j)          = 256 (Im V - S_i)
+//      with S_i = sum_t re_i(t), kept per row with v_dot4 on the unpacked
+//      16*re bytes and added back at the flush.
+// For 8+8-bit input the rows hold int8 re and im separately (no scaling) and
+// the same ~im identity gives accI = Im V - S_i.
+//
+// Exactness: every quantity is an integer; int32 MFMA sums wrap modulo 2^32
+// but each segment is at most SEG_T = 32768 samples, so the final 256 Re V and
+// 256 (Im V - S_i) of a segment stay inside int32 (|Re V|, |Im V| <= 128 T for
+// 4-bit; <= 32768 T unscaled for 8-bit) and the shifts back are exact.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace xeng {
+
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int TK = 64;          // time samples per LDS stage
+constexpr int SEG_T = 32768;    // most samples one launch may integrate
+constexpr int WG_THREADS = 256; // 4 waves in a 2 x 2 grid of wave tiles
+
+struct TileArgs {
+    const uint8_t *samples; // [T][F][N] (4-bit) or [T][F][N][2] (8-bit)
+    int32_t *vis;           // [F][tri(N)][2]
+    int64_t t_begin;        // first sample of this segment
+    int32_t t_count;        // samples in this segment (<= SEG_T)
+    int32_t n_chans;
+    int32_t n_inputs;
+    int32_t n_tiles;        // tiles per channel: nb (nb + 1) / 2
+    int32_t n_work;         // n_tiles * n_chans = grid size
+    int32_t accumulate;     // 0: overwrite the accumulator, 1: add to it
+};
+
+// Byte transpose of a 4x4 block held in 4 dwords: in[s] byte q -> out[q] byte s.
+__device__ __forceinline__ void transpose4x4(uint32_t a, uint32_t b, uint32_t c, uint32_t d,
+                                             uint32_t &o0, uint32_t &o1, uint32_t &o2,
+                                             uint32_t &o3)
+{
+    // __builtin_amdgcn_perm(hi, lo, sel): byte k of the result is byte sel[k]
+    // of the 8-byte value {hi:lo} (bytes 0-3 from lo, 4-7 from hi).
+    const uint32_t lo_ab = __builtin_amdgcn_perm(b, a, 0x05010400u); // a0 b0 a1 b1
+    const uint32_t hi_ab = __builtin_amdgcn_perm(b, a, 0x07030602u); // a2 b2 a3 b3
+    const uint32_t lo_cd = __builtin_amdgcn_perm(d, c, 0x05010400u); // c0 d0 c1 d1
+    const uint32_t hi_cd = __builtin_amdgcn_perm(d, c, 0x07030602u); // c2 d2 c3 d3
+    o0 = __builtin_amdgcn_perm(lo_cd, lo_ab, 0x05040100u);           // a0 b0 c0 d0
+    o1 = __builtin_amdgcn_perm(lo_cd, lo_ab, 0x07060302u);           // a1 b1 c1 d1
+    o2 = __builtin_amdgcn_perm(hi_cd, hi_ab, 0x05040100u);           // a2 b2 c2 d2
+    o3 = __builtin_amdgcn_perm(hi_cd, hi_ab, 0x07060302u);           // a3 b3 c3 d3
+}
+
+// Map a linear workgroup id so that the workgroups one XCD runs (ids
+// congruent mod 8, dispatched round-robin over the 8 XCDs) get consecutive
+// work items, i.e. the tiles of the same channels, which share input rows in
+// that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int bid, int n)
+{
+    const int per = n / 8, rem = n % 8;
+    const int x = bid % 8, k = bid / 8;
+    return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + k;
+}
+
+// Tile index t of the lower block triangle -> (bi, bj), bj <= bi, row-major.
+__device__ __forceinline__ void tri_decode(int t, int &bi, int &bj)
+{
+    int i = (int)((__builtin_sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while (i * (i + 1) / 2 > t) --i;
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    bi = i;
+    bj = t - i * (i + 1) / 2;
+}
+
+// Swizzle of the 16-byte time slots of a staged row, so that 8 lanes reading
+// the same slot of 8 consecutive rows touch 8 different bank groups.
+__device__ __forceinline__ int slot_swz(int row) { return (row >> 1) & 3; }
+
+// IN_BITS = 4: staged row = TK bytes (packed samples).
+// IN_BITS = 8: two staged rows per input (re row, im row), TK bytes each.
+// WT = wave tile edge in 16-row sub-blocks; workgroup tile edge BT = 32 * WT.
+template <int IN_BITS, int WT>
+__global__ __launch_bounds__(WG_THREADS, (IN_BITS == 8 && WT == 4) ? 1 : 2) void xcorr_i8_kernel(TileArgs a)
+{
+    constexpr int BT = 32 * WT;            // workgroup tile edge (inputs)
+    constexpr int HB = BT / 2;             // wave tile edge
+    constexpr int NROW = 2 * BT;           // staged inputs: I block then J block
+    constexpr int RPI = IN_BITS == 4 ? 1 : 2;  // staged rows per input
+    constexpr int ROWB = TK;               // bytes per staged row per stage
+    constexpr int BUF = NROW * RPI * ROWB; // bytes per stage buffer
+    // staging units: groups of 4 (4-bit) or 2 (8-bit) inputs x 16 time samples
+    constexpr int IPU = IN_BITS == 4 ? 4 : 2;
+    constexpr int NGRP = NROW / IPU;
+    constexpr int NUNIT = NGRP * (TK / 16);
+    constexpr int UPT = (NUNIT + WG_THREADS - 1) / WG_THREADS; // units per thread
+
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * BUF];
+    __shared__ int32_t srow[BT];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+
+    const int work = xcd_remap(blockIdx.x, a.n_work);
+    const int f = work / a.n_tiles;
+    int bi, bj;
+    tri_decode(work - f * a.n_tiles, bi, bj);
+    const int I0 = bi * BT, J0 = bj * BT;
+    const bool diag = bi == bj;
+    const int N = a.n_inputs;
+    const int F = a.n_chans;
+    // a wave whose whole tile lies above the diagonal has nothing to compute
+    const bool active = !(diag && wr < wc);
+
+    // ---- staging assignment (fixed over the time loop)
+    constexpr int SB = IN_BITS == 4 ? 1 : 2;            // bytes per complex sample
+    const size_t row_stride = (size_t)F * N * SB;       // bytes per time step
+    const bool aligned = (N & (IN_BITS == 4 ? 3 : 1)) == 0;
+    bool u_on[UPT];
+    int u_blk[UPT], u_row0[UPT], u_gin[UPT];
+    const uint8_t *u_src[UPT];
+#pragma unroll
+    for (int u = 0; u < UPT; ++u) {
+        const int unit = tid + u * WG_THREADS;
+        u_on[u] = unit < NUNIT;
+        const int grp = unit % NGRP;
+        u_blk[u] = unit / NGRP;                          // 16-sample block of the stage
+        u_row0[u] = grp * IPU;                           // first staged input of the group
+        u_gin[u] = u_row0[u] < BT ? I0 + u_row0[u] : J0 + (u_row0[u] - BT);
+        u_src[u] = a.samples + ((size_t)f * N + u_gin[u]) * SB;
+    }
+
+    auto load_stage = [&](int stage, uint32_t (&d)[UPT][16]) {
+#pragma unroll
+        for (int u = 0; u < UPT; ++u) {
+#pragma unroll
+            for (int s = 0; s < 16; ++s) d[u][s] = 0u;
+            if (!u_on[u]) continue;
+            const int t0 = stage * TK + u_blk[u] * 16;
+            const int gin = u_gin[u];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const int tl = t0 + s;
+                if (tl < a.t_count) {
+                    const uint8_t *p = u_src[u] + (size_t)(a.t_begin + tl) * row_stride;
+                    if (aligned && gin + IPU <= N) {
+                        d[u][s] = *(const uint32_t *)p;
+                    } else {
+                        uint32_t v = 0;
+                        for (int b = 0; b < 4; ++b) {
+                            const int in = gin + (IN_BITS == 4 ? b : b / 2);
+                            if (in < N) v |= (uint32_t)p[b] << (8 * b);
+                        }
+                        d[u][s] = v;
+                    }
+                }
+            }
+        }
+    };
+
+    auto store_stage = [&](uint8_t *buf, const uint32_t (&d)[UPT][16]) {
+#pragma unroll
+        for (int u = 0; u < UPT; ++u) {
+            if (!u_on[u]) continue;
+            uint32_t e[4][4]; // e[q][c]: byte column q of 4x4 block c
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                transpose4x4(d[u][4 * c], d[u][4 * c + 1], d[u][4 * c + 2], d[u][4 * c + 3],
+                             e[0][c], e[1][c], e[2][c], e[3][c]);
+            // 4-bit: byte q of a dword is input row0 + q.
+            // 8-bit: byte q is (input row0 + q/2, re if q even else im).
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = IN_BITS == 4 ? u_row0[u] + q : 2 * (u_row0[u] + q / 2) + (q & 1);
+                const int slot = u_blk[u] ^ slot_swz(row);
+                u32x4 v = {e[q][0], e[q][1], e[q][2], e[q][3]};
+                *(u32x4 *)(buf + row * ROWB + slot * 16) = v;
+            }
+        }
+    };
+
+    i32x4 accR[WT][WT], accI[WT][WT];
+#pragma unroll
+    for (int x = 0; x < WT; ++x)
+#pragma unroll
+        for (int y = 0; y < WT; ++y) {
+            accR[x][y] = i32x4{0, 0, 0, 0};
+            accI[x][y] = i32x4{0, 0, 0, 0};
+        }
+    int32_t rsum[WT];
+#pragma unroll
+    for (int x = 0; x < WT; ++x) rsum[x] = 0;
+
+    const int nstage = (a.t_count + TK - 1) / TK;
+    const int kg = lane >> 4;   // k-group: samples 16 kg .. 16 kg + 15 of a stage
+    const int lr = lane & 15;   // row within a 16-row sub-block
+
+    uint32_t d[UPT][16];
+    load_stage(0, d);
+    store_stage(lds, d);
+    __syncthreads();
+
+    for (int st = 0; st < nstage; ++st) {
+        const uint8_t *buf = lds + (st & 1) * BUF;
+        if (st + 1 < nstage) load_stage(st + 1, d);
+
+        if (active) {
+            i32x4 reI[WT], imI[WT];
+#pragma unroll
+            for (int x = 0; x < WT; ++x) {
+                const int in = wr * HB + 16 * x + lr;           // staged input (I block)
+                if (IN_BITS == 4) {
+                    const u32x4 p = *(const u32x4 *)(buf + in * ROWB + ((kg ^ slot_swz(in)) * 16));
+                    reI[x] = (i32x4)(p & 0xF0F0F0F0u);
+                    imI[x] = (i32x4)((p << 4) & 0xF0F0F0F0u);
+                } else {
+                    const int rr = 2 * in, ri = 2 * in + 1;
+                    reI[x] = *(const i32x4 *)(buf + rr * ROWB + ((kg ^ slot_swz(rr)) * 16));
+                    imI[x] = *(const i32x4 *)(buf + ri * ROWB + ((kg ^ slot_swz(ri)) * 16));
+                }
+            }
+            if (wc == 0) {
+#pragma unroll
+                for (int x = 0; x < WT; ++x) {
+                    int s = rsum[x];
+                    s = __builtin_amdgcn_sdot4(reI[x].x, 0x01010101, s, false);
+                    s = __builtin_amdgcn_sdot4(reI[x].y, 0x01010101, s, false);
+                    s = __builtin_amdgcn_sdot4(reI[x].z, 0x01010101, s, false);
+                    s = __builtin_amdgcn_sdot4(reI[x].w, 0x01010101, s, false);
+                    rsum[x] = s;
+                }
+            }
+#pragma unroll
+            for (int y = 0; y < WT; ++y) {
+                const int in = BT + wc * HB + 16 * y + lr;      // staged input (J block)
+                i32x4 reJ, imJ, niJ;
+                if (IN_BITS == 4) {
+                    const u32x4 p = *(const u32x4 *)(buf + in * ROWB + ((kg ^ slot_swz(in)) * 16));
+                    const u32x4 im = (p << 4) & 0xF0F0F0F0u;
+                    reJ = (i32x4)(p & 0xF0F0F0F0u);
+                    imJ = (i32x4)im;
+                    niJ = (i32x4)(im ^ 0xF0F0F0F0u);
+                } else {
+                    const int rr = 2 * in, ri = 2 * in + 1;
+                    reJ = *(const i32x4 *)(buf + rr * ROWB + ((kg ^ slot_swz(rr)) * 16));
+                    imJ = *(const i32x4 *)(buf + ri * ROWB + ((kg ^ slot_swz(ri)) * 16));
+                    niJ = ~imJ;
+                }
+#pragma unroll
+                for (int x = 0; x < WT; ++x) {
+                    accR[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(reI[x], reJ, accR[x][y], 0, 0, 0);
+                    accI[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(reI[x], niJ, accI[x][y], 0, 0, 0);
+                    accR[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(imI[x], imJ, accR[x][y], 0, 0, 0);
+                    accI[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(imI[x], reJ, accI[x][y], 0, 0, 0);
+                }
+            }
+        }
+
+        if (st + 1 < nstage) store_stage(lds + ((st + 1) & 1) * BUF, d);
+        __syncthreads();
+    }
+
+    // ---- row sums S_i of the I block (scaled by 16 for 4-bit input)
+    if (wc == 0) {
+#pragma unroll
+        for (int x = 0; x < WT; ++x) {
+            int s = rsum[x];
+            s += __shfl_xor(s, 16);
+            s += __shfl_xor(s, 32);
+            if (lane < 16) srow[wr * HB + 16 * x + lane] = s;
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+
+    // ---- flush: 16x16 MFMA result layout, lane holds column (lane & 15) of
+    // rows 4 (lane >> 4) + r, r = 0..3
+    const int64_t tri = (int64_t)N * (N + 1) / 2;
+    int2 *vis = (int2 *)a.vis + (size_t)f * (size_t)tri;
+#pragma unroll
+    for (int x = 0; x < WT; ++x)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int rl = wr * HB + 16 * x + 4 * kg + r;
+            const int i = I0 + rl;
+            if (i >= N) continue;
+            const int32_t s = srow[rl];
+            const int32_t scorr = IN_BITS == 4 ? (s >> 4) : s;
+            const int64_t rowbase = (int64_t)i * (i + 1) / 2;
+#pragma unroll
+            for (int y = 0; y < WT; ++y) {
+                const int j = J0 + wc * HB + 16 * y + lr;
+                if (j > i) continue;
+                int32_t re, im;
+                if (IN_BITS == 4) {
+                    re = accR[x][y][r] >> 8;
+                    im = (accI[x][y][r] >> 8) + scorr;
+                } else {
+                    re = accR[x][y][r];
+                    im = accI[x][y][r] + scorr;
+                }
+                int2 *p = vis + rowbase + j;
+                if (a.accumulate) {
+                    int2 o = *p;
+                    o.x += re;
+                    o.y += im;
+                    *p = o;
+                } else {
+                    *p = make_int2(re, im);
+                }
+            }
+        }
+}
+
+// Clear n int32 words (used instead of a memset so that the work can sit in a
+// captured graph).
+__global__ void fill_zero_kernel(int4 *p, size_t n16, int32_t *tail, size_t ntail)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += stride)
+        p[k] = make_int4(0, 0, 0, 0);
+    if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+} // namespace xeng

@@ -1,0 +1,212 @@
+"""Thin ctypes binding of libxeng.so (include/xeng.h).
+
+Argument marshalling only: every step of the correlation runs in the HIP
+library. PyTorch supplies device memory (tensors) and streams. If the built
+library is missing this module raises at load time; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libxeng.so")
+
+XENG_OK, XENG_EINVAL, XENG_ERANGE, XENG_ENOMEM, XENG_EHIP = 0, 1, 2, 3, 4
+ENGINE_I8, ENGINE_FP8 = 0, 1
+MAX_DUMP_SAMPLES_4BIT = 16777215
+MAX_DUMP_SAMPLES_8BIT = 65535
+MAX_CALL_SAMPLES_FP8 = 32768
+
+EXPORTS = (
+    "xeng_create", "xeng_correlate", "xeng_dump", "xeng_destroy", "xeng_set_stream",
+    "xeng_samples_since_dump", "xeng_max_dump_samples", "xeng_plan_describe",
+    "xeng_strerror", "xeng_last_error",
+)
+
+
+class XengError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("xeng error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Subarray(ctypes.Structure):
+    _fields_ = [("n_inputs", ctypes.c_int32), ("n_chans", ctypes.c_int32),
+                ("n_time", ctypes.c_int32), ("in_bits", ctypes.c_int32),
+                ("engine", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libxeng.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libxeng.so is not built (%s); run python -m paper_1411_3751_amd.build"
+                          % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    lib.xeng_create.argtypes = [ctypes.POINTER(Subarray), i32, vp, ctypes.POINTER(vp)]
+    lib.xeng_create.restype = i32
+    lib.xeng_correlate.argtypes = [vp, pp]
+    lib.xeng_correlate.restype = i32
+    lib.xeng_dump.argtypes = [vp, pp, i32, i32]
+    lib.xeng_dump.restype = i32
+    lib.xeng_destroy.argtypes = [vp]
+    lib.xeng_destroy.restype = i32
+    lib.xeng_set_stream.argtypes = [vp, vp]
+    lib.xeng_set_stream.restype = i32
+    lib.xeng_samples_since_dump.argtypes = [vp, i32, ctypes.POINTER(i64)]
+    lib.xeng_samples_since_dump.restype = i32
+    lib.xeng_max_dump_samples.argtypes = [vp, i32, ctypes.POINTER(i64)]
+    lib.xeng_max_dump_samples.restype = i32
+    lib.xeng_plan_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+    lib.xeng_plan_describe.restype = i32
+    lib.xeng_strerror.argtypes = [i32]
+    lib.xeng_strerror.restype = ctypes.c_char_p
+    lib.xeng_last_error.argtypes = []
+    lib.xeng_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != XENG_OK:
+        lib = load()
+        raise XengError(rc, "%s: %s" % (lib.xeng_strerror(rc).decode(),
+                                        lib.xeng_last_error().decode()))
+
+
+def tri(n: int) -> int:
+    return n * (n + 1) // 2
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _ptrs(values):
+    arr = (ctypes.c_void_p * len(values))()
+    for k, v in enumerate(values):
+        arr[k] = v
+    return arr
+
+
+class Correlator:
+    """X-engine context over one or more subarrays (dicts or Subarray)."""
+
+    def __init__(self, subarrays, stream=None):
+        subs = []
+        for s in subarrays:
+            if isinstance(s, Subarray):
+                subs.append(s)
+            else:
+                subs.append(Subarray(int(s["n_inputs"]), int(s["n_chans"]), int(s["n_time"]),
+                                     int(s.get("in_bits", 4)), int(s.get("engine", ENGINE_I8))))
+        self.subs = subs
+        arr = (Subarray * len(subs))(*subs)
+        self._lib = load()
+        self._ctx = ctypes.c_void_p()
+        _check(self._lib.xeng_create(arr, len(subs), ctypes.c_void_p(_stream_handle(stream)),
+                                     ctypes.byref(self._ctx)))
+
+    # -- shapes
+    def sample_shape(self, k: int):
+        s = self.subs[k]
+        base = (s.n_time, s.n_chans, s.n_inputs)
+        return base if s.in_bits == 4 else base + (2,)
+
+    def vis_shape(self, k: int):
+        s = self.subs[k]
+        return (s.n_chans, tri(s.n_inputs), 2)
+
+    # -- calls
+    def set_stream(self, stream):
+        _check(self._lib.xeng_set_stream(self._ctx, ctypes.c_void_p(_stream_handle(stream))))
+
+    def correlate(self, samples):
+        """samples: one device tensor (or device pointer int) per subarray."""
+        if not isinstance(samples, (list, tuple)):
+            samples = [samples]
+        if len(samples) != len(self.subs):
+            raise ValueError("need one sample buffer per subarray")
+        ptrs = []
+        for k, x in enumerate(samples):
+            if isinstance(x, int):
+                ptrs.append(x)
+                continue
+            s = self.subs[k]
+            want = self.sample_shape(k)
+            if tuple(x.shape) != want:
+                raise ValueError("subarray %d: samples shape %s, expected %s" % (k, tuple(x.shape), want))
+            if not x.is_cuda or not x.is_contiguous() or x.element_size() != 1:
+                raise ValueError("subarray %d: samples must be a contiguous 1-byte device tensor" % k)
+            ptrs.append(x.data_ptr())
+        _check(self._lib.xeng_correlate(self._ctx, _ptrs(ptrs)))
+
+    def dump(self, out=None, reset: bool = True, device: bool = True):
+        """Copy the sums into out (allocated if None); returns the list of outputs."""
+        import torch
+        if out is None:
+            dev = torch.device("cuda", torch.cuda.current_device()) if device else torch.device("cpu")
+            out = [torch.empty(self.vis_shape(k), dtype=torch.int32, device=dev,
+                               pin_memory=(not device))
+                   for k in range(len(self.subs))]
+        elif not isinstance(out, (list, tuple)):
+            out = [out]
+        ptrs = []
+        for k, o in enumerate(out):
+            if tuple(o.shape) != self.vis_shape(k) or o.dtype != torch.int32 or not o.is_contiguous():
+                raise ValueError("subarray %d: output must be contiguous int32 %s" % (k, self.vis_shape(k)))
+            if o.is_cuda != device:
+                raise ValueError("subarray %d: output device does not match device=%s" % (k, device))
+            ptrs.append(o.data_ptr())
+        _check(self._lib.xeng_dump(self._ctx, _ptrs(ptrs), 1 if device else 0, 1 if reset else 0))
+        return out
+
+    def reset(self):
+        _check(self._lib.xeng_dump(self._ctx, None, 1, 1))
+
+    def samples_since_dump(self, k: int = 0) -> int:
+        v = ctypes.c_int64()
+        _check(self._lib.xeng_samples_since_dump(self._ctx, k, ctypes.byref(v)))
+        return v.value
+
+    def max_dump_samples(self, k: int = 0) -> int:
+        v = ctypes.c_int64()
+        _check(self._lib.xeng_max_dump_samples(self._ctx, k, ctypes.byref(v)))
+        return v.value
+
+    def plan(self) -> dict:
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(self._lib.xeng_plan_describe(self._ctx, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            rc = self._lib.xeng_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+            _check(rc)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,149 @@
+"""Parity of the HIP X-engine with the CPU oracle (bit-exact), through the C ABI.
+
+Every case prints its shape before running so that a failure names it.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def rand_stream(rng, T, F, N, in_bits, lo=None, hi=None):
+    if in_bits == 4:
+        lo = -8 if lo is None else lo
+        hi = 7 if hi is None else hi
+        re = rng.integers(lo, hi + 1, size=(T, F, N)).astype(np.int8)
+        im = rng.integers(lo, hi + 1, size=(T, F, N)).astype(np.int8)
+        return synth.pack4(re, im)
+    lo = -128 if lo is None else lo
+    hi = 127 if hi is None else hi
+    re = rng.integers(lo, hi + 1, size=(T, F, N)).astype(np.int8)
+    im = rng.integers(lo, hi + 1, size=(T, F, N)).astype(np.int8)
+    return synth.pack8(re, im)
+
+
+def gpu_once(torch, samples, in_bits, engine=0):
+    from paper_1411_3751_amd import Correlator
+    T, F, N = samples.shape[:3]
+    d = torch.from_numpy(samples).cuda()
+    with Correlator([dict(n_inputs=N, n_chans=F, n_time=T, in_bits=in_bits, engine=engine)]) as c:
+        c.correlate([d])
+        out = c.dump()[0]
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
+
+
+SHAPES = [
+    # (N, F, T): tile variants (N <= 32, <= 64, > 64), ragged N and T, several tiles
+    (1, 2, 1), (2, 3, 7), (5, 2, 63), (31, 3, 64), (32, 2, 65), (33, 2, 100),
+    (64, 2, 129), (65, 2, 64), (100, 3, 200), (128, 2, 256), (130, 2, 77),
+    (200, 2, 300), (257, 1, 130), (384, 1, 64),
+]
+
+
+@pytest.mark.parametrize("in_bits", [4, 8])
+@pytest.mark.parametrize("N,F,T", SHAPES)
+def test_parity_random(torch_cuda, oracle_lib, N, F, T, in_bits):
+    print("case N=%d F=%d T=%d in_bits=%d" % (N, F, T, in_bits), flush=True)
+    rng = np.random.default_rng(N * 1000 + F * 10 + T + in_bits)
+    s = rand_stream(rng, T, F, N, in_bits)
+    want = oracle_lib.narrow(oracle_lib.correlate(s, in_bits))
+    got = gpu_once(torch_cuda, s, in_bits)
+    assert got.shape == want.shape
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, "first mismatches %s" % bad[:5].tolist()
+
+
+@pytest.mark.parametrize("in_bits,code", [(4, 0x88), (4, 0x77), (4, 0x8F), (8, -128), (8, 127)])
+def test_extreme_values(torch_cuda, oracle_lib, in_bits, code):
+    # saturated inputs (all -8-8i, 7+7i, ...) exercise the largest products
+    print("case extremes in_bits=%d code=%d" % (in_bits, code), flush=True)
+    T, F, N = 300, 2, 70
+    if in_bits == 4:
+        s = np.full((T, F, N), code, np.uint8)
+    else:
+        s = np.full((T, F, N, 2), code, np.int8)
+    want = oracle_lib.narrow(oracle_lib.correlate(s, in_bits))
+    assert np.array_equal(gpu_once(torch_cuda, s, in_bits), want)
+
+
+def test_tiny_workload(torch_cuda, oracle_lib):
+    # N=32 inputs, 16 channels, 1024 samples, quantised Gaussian (sigma 2.5)
+    s, _, _, _ = synth.workload("tiny")
+    want = oracle_lib.narrow(oracle_lib.correlate(s, 4))
+    assert np.array_equal(gpu_once(torch_cuda, s, 4), want)
+
+
+def test_multi_segment_call(torch_cuda, oracle_lib):
+    # a call longer than one launch segment (32768 samples) is split and summed
+    print("case multi-segment", flush=True)
+    rng = np.random.default_rng(99)
+    s = rand_stream(rng, 70000, 1, 40, 4)
+    want = oracle_lib.narrow(oracle_lib.correlate(s, 4))
+    assert np.array_equal(gpu_once(torch_cuda, s, 4), want)
+
+
+def test_accumulate_dump_reset(torch_cuda, oracle_lib):
+    from paper_1411_3751_amd import Correlator
+    torch = torch_cuda
+    rng = np.random.default_rng(5)
+    T, F, N = 96, 3, 150
+    gulps = [rand_stream(rng, T, F, N, 4) for _ in range(3)]
+    with Correlator([dict(n_inputs=N, n_chans=F, n_time=T)]) as c:
+        # a dump before any data is all zeros
+        assert not c.dump()[0].cpu().numpy().any()
+        for g in gulps:
+            c.correlate([torch.from_numpy(g).cuda()])
+        assert c.samples_since_dump() == 3 * T
+        # snapshot without reset keeps integrating
+        snap = c.dump(reset=False)[0].cpu().numpy()
+        acc = np.zeros((F, N * (N + 1) // 2, 2), np.int64)
+        for g in gulps:
+            oracle_lib.accumulate(acc, g, 4)
+        assert np.array_equal(snap, oracle_lib.narrow(acc))
+        c.correlate([torch.from_numpy(gulps[0]).cuda()])
+        oracle_lib.accumulate(acc, gulps[0], 4)
+        host = c.dump(device=False)[0].numpy()
+        assert np.array_equal(host, oracle_lib.narrow(acc))
+        assert c.samples_since_dump() == 0
+        # after the reset the next integration starts from zero
+        c.correlate([torch.from_numpy(gulps[1]).cuda()])
+        assert np.array_equal(c.dump()[0].cpu().numpy(),
+                              oracle_lib.narrow(oracle_lib.correlate(gulps[1], 4)))
+
+
+def test_repeatable_bits(torch_cuda):
+    # integer results do not depend on order: repeated runs give identical bits
+    rng = np.random.default_rng(6)
+    s = rand_stream(rng, 512, 4, 300, 4)
+    a = gpu_once(torch_cuda, s, 4)
+    b = gpu_once(torch_cuda, s, 4)
+    assert np.array_equal(a, b)
+
+
+def test_leda_gulp_sampled_channels(torch_cuda, oracle_lib):
+    # full-size LEDA gulp (N=512, F=128, T=8192, tone in 4 channels), the launch
+    # configuration the benchmark times; the oracle checks the tone channels and
+    # 4 seeded-random channels in full, the projection check covers 16 more
+    print("case leda_gulp full size", flush=True)
+    s, _, _, meta = synth.workload("leda_gulp")
+    got = gpu_once(torch_cuda, s, 4)
+    rng = np.random.default_rng(2024)
+    chans = synth.tone_channels(128) + sorted(rng.choice(
+        [f for f in range(128) if f not in synth.tone_channels(128)], 4, replace=False).tolist())
+    want = oracle_lib.narrow(oracle_lib.correlate(s, 4, chans=chans))
+    assert np.array_equal(got[chans], want)
+    others = [f for f in range(128) if f not in chans]
+    for f in rng.choice(others, 16, replace=False):
+        w = rng.integers(-4, 5, size=(512, 2)).astype(np.int64)
+        assert oracle_lib.projection_check(s, 4, int(f), got[f], w) == 0
