@@ -66,16 +66,31 @@ namespace {
 
 using KernelFn = void (*)(xeng::TileArgs);
 
-KernelFn pick_kernel(int in_bits, int wt)
+template <int IN_BITS, bool AL>
+KernelFn pick_wt(int wt)
 {
-    if (in_bits == 4) {
-        if (wt == 1) return xeng::xcorr_i8_kernel<4, 1>;
-        if (wt == 2) return xeng::xcorr_i8_kernel<4, 2>;
-        return xeng::xcorr_i8_kernel<4, 4>;
+    if (wt == 1) return xeng::xcorr_i8_kernel<IN_BITS, 1, AL>;
+    if (wt == 2) return xeng::xcorr_i8_kernel<IN_BITS, 2, AL>;
+    return xeng::xcorr_i8_kernel<IN_BITS, 4, AL>;
+}
+
+constexpr int DMA_NBUF = 4; // LDS ring depth of the direct-staging kernel
+
+// 4-bit input whose rows split into whole 16-byte chunks takes the
+// direct-staging kernel; everything else the register-staging kernel (whole
+// dword loads when a dword holds whole inputs, else byte loads).
+bool use_dma(int in_bits, int n_inputs) { return in_bits == 4 && n_inputs % 16 == 0; }
+
+KernelFn pick_kernel(int in_bits, int wt, int n_inputs)
+{
+    if (use_dma(in_bits, n_inputs)) {
+        if (wt == 1) return xeng::xcorr4_dma_kernel<1, DMA_NBUF>;
+        if (wt == 2) return xeng::xcorr4_dma_kernel<2, DMA_NBUF>;
+        return xeng::xcorr4_dma_kernel<4, DMA_NBUF>;
     }
-    if (wt == 1) return xeng::xcorr_i8_kernel<8, 1>;
-    if (wt == 2) return xeng::xcorr_i8_kernel<8, 2>;
-    return xeng::xcorr_i8_kernel<8, 4>;
+    if (in_bits == 4)
+        return (n_inputs % 4 == 0) ? pick_wt<4, true>(wt) : pick_wt<4, false>(wt);
+    return (n_inputs % 2 == 0) ? pick_wt<8, true>(wt) : pick_wt<8, false>(wt);
 }
 
 // Tile edge per input count: the smallest workgroup tile that covers N, up
@@ -110,6 +125,10 @@ int validate(const xeng_subarray &s, int idx)
     const int64_t nb = (s.n_inputs + 127) / 128;
     if (tri * (int64_t)s.n_chans * 2 > ((int64_t)1 << 40) || nb * (nb + 1) / 2 * s.n_chans > INT32_MAX)
         return fail(XENG_EINVAL, "subarray %d: output too large", idx);
+    // one LDS stage of the tile kernel spans TK time rows of the whole
+    // [F][N] plane; its byte offsets must fit the 32-bit buffer offsets
+    if ((int64_t)s.n_chans * s.n_inputs * (s.in_bits / 4) * xeng::TK >= ((int64_t)1 << 31))
+        return fail(XENG_EINVAL, "subarray %d: n_chans * n_inputs too large for one stream", idx);
     const int64_t bound = s.in_bits == 4 ? XENG_MAX_DUMP_SAMPLES_4BIT : XENG_MAX_DUMP_SAMPLES_8BIT;
     if (s.n_time > bound)
         return fail(XENG_EINVAL, "subarray %d: n_time %d above the dump limit %lld", idx, s.n_time,
@@ -132,7 +151,7 @@ int zero_device(int32_t *p, size_t n_words, hipStream_t st)
 int launch_sub(Sub &s, const void *d_samples, hipStream_t st)
 {
     const xeng_subarray &c = s.cfg;
-    KernelFn fn = pick_kernel(c.in_bits, s.wt);
+    KernelFn fn = pick_kernel(c.in_bits, s.wt, c.n_inputs);
     for (int64_t t0 = 0; t0 < c.n_time; t0 += xeng::SEG_T) {
         xeng::TileArgs a;
         a.samples = (const uint8_t *)d_samples;
@@ -313,10 +332,11 @@ int xeng_plan_describe(const xeng_ctx *ctx, char *buf, size_t len)
         const int64_t segs = (s.cfg.n_time + xeng::SEG_T - 1) / xeng::SEG_T;
         snprintf(item, sizeof item,
                  "%s{\"n_inputs\": %d, \"n_chans\": %d, \"n_time\": %d, \"in_bits\": %d, "
-                 "\"engine\": \"%s\", \"tile\": %d, \"wave_tile\": %d, \"tiles_per_chan\": %d, "
+                 "\"engine\": \"%s\", \"staging\": \"%s\", \"tile\": %d, \"wave_tile\": %d, \"tiles_per_chan\": %d, "
                  "\"workgroups\": %lld, \"launches_per_call\": %lld}",
                  k ? ", " : "", s.cfg.n_inputs, s.cfg.n_chans, s.cfg.n_time, s.cfg.in_bits,
-                 s.cfg.engine == XENG_ENGINE_I8 ? "i8" : "fp8", s.bt, s.bt / 2, s.n_tiles,
+                 s.cfg.engine == XENG_ENGINE_I8 ? "i8" : "fp8",
+                 use_dma(s.cfg.in_bits, s.cfg.n_inputs) ? "lds_dma" : "registers", s.bt, s.bt / 2, s.n_tiles,
                  (long long)s.n_tiles * s.cfg.n_chans, (long long)segs);
         js += item;
     }

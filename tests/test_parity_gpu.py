@@ -48,6 +48,9 @@ SHAPES = [
     (1, 2, 1), (2, 3, 7), (5, 2, 63), (31, 3, 64), (32, 2, 65), (33, 2, 100),
     (64, 2, 129), (65, 2, 64), (100, 3, 200), (128, 2, 256), (130, 2, 77),
     (200, 2, 300), (257, 1, 130), (384, 1, 64),
+    # multiples of 16 (direct LDS staging for 4-bit): tails, partial tiles, diagonal tiles
+    (16, 3, 5), (48, 2, 70), (96, 2, 64), (144, 2, 100), (160, 2, 33), (256, 3, 1000),
+    (512, 1, 200),
 ]
 
 
