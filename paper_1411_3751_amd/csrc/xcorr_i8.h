@@ -115,7 +115,6 @@ __global__ __launch_bounds__(WG_THREADS, (IN_BITS == 8 && WT == 4) ? 1 : 2) void
     constexpr int UPT = (NUNIT + WG_THREADS - 1) / WG_THREADS; // units per thread
 
     __shared__ __attribute__((aligned(16))) uint8_t lds[2 * BUF];
-    __shared__ int32_t srow[BT];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -221,9 +220,6 @@ __global__ __launch_bounds__(WG_THREADS, (IN_BITS == 8 && WT == 4) ? 1 : 2) void
             accR[x][y] = i32x4{0, 0, 0, 0};
             accI[x][y] = i32x4{0, 0, 0, 0};
         }
-    int32_t rsum[WT];
-#pragma unroll
-    for (int x = 0; x < WT; ++x) rsum[x] = 0;
 
     const int nstage = (a.t_count + TK - 1) / TK;
     const int kg = lane >> 4;   // k-group: samples 16 kg .. 16 kg + 15 of a stage
@@ -251,17 +247,6 @@ __global__ __launch_bounds__(WG_THREADS, (IN_BITS == 8 && WT == 4) ? 1 : 2) void
                     const int rr = 2 * in, ri = 2 * in + 1;
                     reI[x] = *(const i32x4 *)(buf + rr * ROWB + ((kg ^ slot_swz(rr)) * 16));
                     imI[x] = *(const i32x4 *)(buf + ri * ROWB + ((kg ^ slot_swz(ri)) * 16));
-                }
-            }
-            if (wc == 0) {
-#pragma unroll
-                for (int x = 0; x < WT; ++x) {
-                    int s = rsum[x];
-                    s = __builtin_amdgcn_sdot4(reI[x].x, 0x01010101, s, false);
-                    s = __builtin_amdgcn_sdot4(reI[x].y, 0x01010101, s, false);
-                    s = __builtin_amdgcn_sdot4(reI[x].z, 0x01010101, s, false);
-                    s = __builtin_amdgcn_sdot4(reI[x].w, 0x01010101, s, false);
-                    rsum[x] = s;
                 }
             }
 #pragma unroll
@@ -294,23 +279,12 @@ __global__ __launch_bounds__(WG_THREADS, (IN_BITS == 8 && WT == 4) ? 1 : 2) void
         __syncthreads();
     }
 
-    // ---- row sums S_i of the I block (scaled by 16 for 4-bit input)
-    if (wc == 0) {
-#pragma unroll
-        for (int x = 0; x < WT; ++x) {
-            int s = rsum[x];
-            s += __shfl_xor(s, 16);
-            s += __shfl_xor(s, 32);
-            if (lane < 16) srow[wr * HB + 16 * x + lane] = s;
-        }
-    }
-    __syncthreads();
     if (!active) return;
 
     // ---- flush: 16x16 MFMA result layout, lane holds column (lane & 15) of
     // rows 4 (lane >> 4) + r, r = 0..3
     const int64_t tri = (int64_t)N * (N + 1) / 2;
-    int2 *vis = (int2 *)a.vis + (size_t)f * (size_t)tri;
+    uint2 *vis = (uint2 *)a.vis + (size_t)f * (size_t)tri;
 #pragma unroll
     for (int x = 0; x < WT; ++x)
 #pragma unroll
@@ -318,29 +292,20 @@ __global__ __launch_bounds__(WG_THREADS, (IN_BITS == 8 && WT == 4) ? 1 : 2) void
             const int rl = wr * HB + 16 * x + 4 * kg + r;
             const int i = I0 + rl;
             if (i >= N) continue;
-            const int32_t s = srow[rl];
-            const int32_t scorr = IN_BITS == 4 ? (s >> 4) : s;
             const int64_t rowbase = (int64_t)i * (i + 1) / 2;
 #pragma unroll
             for (int y = 0; y < WT; ++y) {
                 const int j = J0 + wc * HB + 16 * y + lr;
                 if (j > i) continue;
-                int32_t re, im;
-                if (IN_BITS == 4) {
-                    re = accR[x][y][r] >> 8;
-                    im = (accI[x][y][r] >> 8) + scorr;
-                } else {
-                    re = accR[x][y][r];
-                    im = accI[x][y][r] + scorr;
-                }
-                int2 *p = vis + rowbase + j;
+                // raw convention: Im holds Im V - S_i, corrected at the dump
+                const uint32_t re = (uint32_t)(IN_BITS == 4 ? accR[x][y][r] >> 8 : accR[x][y][r]);
+                const uint32_t im = (uint32_t)(IN_BITS == 4 ? accI[x][y][r] >> 8 : accI[x][y][r]);
+                uint2 *p = vis + rowbase + j;
                 if (a.accumulate) {
-                    int2 o = *p;
-                    o.x += re;
-                    o.y += im;
-                    *p = o;
+                    const uint2 o = *p;
+                    *p = make_uint2(o.x + re, o.y + im);
                 } else {
-                    *p = make_int2(re, im);
+                    *p = make_uint2(re, im);
                 }
             }
         }
@@ -356,27 +321,25 @@ __global__ void fill_zero_kernel(int4 *p, size_t n16, int32_t *tail, size_t ntai
     if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = 0;
 }
 
-} // namespace xeng
 
-namespace xeng {
-
-// ---------------------------------------------------------------------------
-// 4-bit tile kernel with direct global->LDS staging (N a multiple of 16).
-//
-// Each stage of TK time rows is copied raw ([time][I block | J block], one
-// byte per complex sample, as it sits in HBM) into an NBUF-deep LDS ring by
-// buffer loads that write LDS directly (16 bytes per lane), so staging takes
-// no registers and no VALU, and NBUF - 1 stages are in flight while one is
-// consumed. The MFMA fragments are read with the LDS transpose load
-// ds_read_b64_tr_b8: in each group of 16 lanes, lane 2m + h names row m of
-// half h (8 bytes: inputs 8h .. 8h + 7 of a 16-input chunk at one time), and
-// lane 8h + j receives byte j of those 8 rows, i.e. input 8h + j at 8
-// consecutive times, which is the K-major operand the MFMA wants.
-//
-// Bank layout: a row holds CH 16-byte chunks; chunk c of time row tau is
-// stored at slot c ^ (tau & 7), so the 8 rows one transpose load touches hit
-// 8 different bank groups.
-// ---------------------------------------------------------------------------
+// Dump of a raw accumulator into the output convention: Re unchanged,
+// Im V_ij = raw_ij - raw_ii (the diagonal entry of row i holds -S_i).
+// Arithmetic is modulo 2^32; the true value fits int32. One thread per
+// output word pair, any grid.
+__global__ void dump_kernel(const uint32_t *acc, uint32_t *out, int64_t n_words2, int64_t tri)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_words2; e += stride) {
+        const int64_t f = e / tri, k = e - f * tri;
+        int64_t i = (int64_t)((__builtin_sqrt(8.0 * (double)k + 1.0) - 1.0) * 0.5);
+        while (i * (i + 1) / 2 > k) --i;
+        while ((i + 1) * (i + 2) / 2 <= k) ++i;
+        const int64_t d = f * tri + i * (i + 1) / 2 + i;
+        const uint2 v = ((const uint2 *)acc)[e];
+        const uint32_t sd = ((const uint32_t *)acc)[2 * d + 1];
+        ((uint2 *)out)[e] = make_uint2(v.x, v.y - sd);
+    }
+}
 
 // The LDS DMA is issued from inline assembly so that the compiler does not
 // see an asynchronous LDS write: left to itself it waits for every
@@ -390,220 +353,27 @@ namespace xeng {
 // lds_addr + 16 l (lds_addr must be wave-uniform).
 __device__ __forceinline__ void dma16(i32x4 rsrc, uint32_t voff, uint32_t lds_addr)
 {
+    // the descriptor and the LDS address are wave-uniform; make that explicit
+    const i32x4 sr = {__builtin_amdgcn_readfirstlane(rsrc.x), __builtin_amdgcn_readfirstlane(rsrc.y),
+                      __builtin_amdgcn_readfirstlane(rsrc.z), __builtin_amdgcn_readfirstlane(rsrc.w)};
     asm volatile("s_mov_b32 m0, %2\n\t"
                  "s_nop 0\n\t"
                  "buffer_load_dwordx4 %0, %1, 0 offen lds"
                  :
-                 : "v"(voff), "s"(rsrc), "s"(__builtin_amdgcn_readfirstlane(lds_addr))
+                 : "v"(voff), "s"(sr), "s"(__builtin_amdgcn_readfirstlane(lds_addr))
                  : "memory");
 }
 
-// Wait until at most N of this wave's DMAs are outstanding, then barrier.
-// The memory clobber keeps the compiler from moving LDS accesses across it.
+// Wait until at most N of this wave's vector-memory operations are
+// outstanding. The memory clobber keeps the compiler from moving LDS
+// accesses across the wait.
 template <int N>
-__device__ __forceinline__ void dma_wait_barrier()
+__device__ __forceinline__ void dma_wait()
 {
-    asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" : : "n"(N) : "memory");
+    asm volatile("s_waitcnt vmcnt(%0)" : : "n"(N) : "memory");
 }
 
 typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) i32x2 lds_i32x2;
-
-template <int WT, int NBUF>
-__global__ __launch_bounds__(WG_THREADS, 2) void xcorr4_dma_kernel(TileArgs a)
-{
-    constexpr int BT = 32 * WT;            // workgroup tile edge (inputs)
-    constexpr int HB = BT / 2;             // wave tile edge
-    constexpr int ROWB = 2 * BT;           // bytes per staged time row: I block | J block
-    constexpr int CH = ROWB / 16;          // 16-byte chunks per row
-    constexpr int HCH = CH / 2;            // chunks per block
-    constexpr int STAGE = TK * ROWB;       // bytes per stage
-    constexpr int LPS = STAGE / 16 / WG_THREADS; // 16-byte loads per thread per stage
-    static_assert(LPS >= 1 && LPS * 16 * WG_THREADS == STAGE, "stage must split evenly");
-    constexpr int SWZ = CH < 8 ? CH - 1 : 7;
-
-    __shared__ __attribute__((aligned(16))) uint8_t lds[NBUF * STAGE];
-    __shared__ int32_t srow[BT];
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
-
-    const int work = xcd_remap(blockIdx.x, a.n_work);
-    const int f = work / a.n_tiles;
-    int bi, bj;
-    tri_decode(work - f * a.n_tiles, bi, bj);
-    const int I0 = bi * BT, J0 = bj * BT;
-    const bool diag = bi == bj;
-    const int N = a.n_inputs;
-    const int F = a.n_chans;
-    const bool active = !(diag && wr < wc);
-    const uint32_t row_stride = (uint32_t)F * (uint32_t)N;
-
-    // ---- DMA assignment: load k of this thread fills 16-byte slot P of the stage
-    constexpr uint32_t OOR = 0x80000000u;
-    uint32_t voff[LPS];
-#pragma unroll
-    for (int k = 0; k < LPS; ++k) {
-        const int P = k * WG_THREADS + tid;
-        const int tau = P / CH, slot = P % CH;
-        const int c = slot ^ (tau & SWZ);
-        const int in = c < HCH ? I0 + 16 * c : J0 + 16 * (c - HCH);
-        // a diagonal tile reads its J fragments from the I chunks, so its J
-        // chunks are not fetched (out-of-range offset, no memory access)
-        const bool on = in < N && !(diag && c >= HCH);
-        voff[k] = on ? (uint32_t)tau * row_stride + (uint32_t)in : OOR;
-    }
-
-    const int nstage = (a.t_count + TK - 1) / TK;
-    const uint32_t lds_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)lds;
-    auto issue = [&](int stage) {
-        const int t_first = stage * TK;
-        const int nt = a.t_count - t_first < TK ? a.t_count - t_first : TK;
-        const uint64_t base = (uint64_t)(uintptr_t)(a.samples +
-                              ((size_t)(a.t_begin + t_first) * F + f) * (size_t)N);
-        const i32x4 rsrc = {(int)(uint32_t)base, (int)((uint32_t)(base >> 32) & 0xFFFFu),
-                            (int)((uint32_t)nt * row_stride), 0x00020000};
-        const uint32_t dst = lds_base + (uint32_t)((stage % NBUF) * STAGE);
-#pragma unroll
-        for (int k = 0; k < LPS; ++k)
-            dma16(rsrc, voff[k], dst + (uint32_t)((k * WG_THREADS + wave * 64) * 16));
-    };
-
-    i32x4 accR[WT][WT], accI[WT][WT];
-#pragma unroll
-    for (int x = 0; x < WT; ++x)
-#pragma unroll
-        for (int y = 0; y < WT; ++y) {
-            accR[x][y] = i32x4{0, 0, 0, 0};
-            accI[x][y] = i32x4{0, 0, 0, 0};
-        }
-    int32_t rsum[WT];
-#pragma unroll
-    for (int x = 0; x < WT; ++x) rsum[x] = 0;
-
-    // transpose-load addressing (fixed): lane = 16 g + 2 m + h
-    const int g = lane >> 4, m = (lane >> 1) & 7, h = lane & 1;
-    const int jc0 = diag ? 0 : HCH;
-
-#pragma unroll
-    for (int s = 0; s < NBUF - 1; ++s)
-        if (s < nstage) issue(s);
-
-    for (int st = 0; st < nstage; ++st) {
-        // this wave's loads of stage st are done once at most the later
-        // stages' loads are outstanding; the barrier publishes everyone's
-        if (st + NBUF - 2 < nstage) dma_wait_barrier<(NBUF - 2) * LPS>();
-        else dma_wait_barrier<0>();
-        uint8_t *buf = lds + (st % NBUF) * STAGE;
-        const int nt = a.t_count - st * TK;
-        if (nt < TK) {
-            // zero the time rows past the end of the segment
-            for (int o = tid * 16; o < STAGE; o += WG_THREADS * 16)
-                if (o / ROWB >= nt) *(u32x4 *)(buf + o) = u32x4{0u, 0u, 0u, 0u};
-            __syncthreads();
-        }
-        if (st + NBUF - 1 < nstage) issue(st + NBUF - 1);
-
-        if (active) {
-            i32x4 reI[WT], imI[WT];
-#pragma unroll
-            for (int x = 0; x < WT; ++x) {
-                const int c = wr * WT + x;
-                u32x4 p;
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    const int tau = 16 * g + 8 * i + m;
-                    const i32x2 v = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
-                        (lds_i32x2 *)(buf + tau * ROWB + 16 * (c ^ (tau & SWZ)) + 8 * h));
-                    p[2 * i] = (uint32_t)v.x;
-                    p[2 * i + 1] = (uint32_t)v.y;
-                }
-                reI[x] = (i32x4)(p & 0xF0F0F0F0u);
-                imI[x] = (i32x4)((p << 4) & 0xF0F0F0F0u);
-            }
-            if (wc == 0) {
-#pragma unroll
-                for (int x = 0; x < WT; ++x) {
-                    int s = rsum[x];
-                    s = __builtin_amdgcn_sdot4(reI[x].x, 0x01010101, s, false);
-                    s = __builtin_amdgcn_sdot4(reI[x].y, 0x01010101, s, false);
-                    s = __builtin_amdgcn_sdot4(reI[x].z, 0x01010101, s, false);
-                    s = __builtin_amdgcn_sdot4(reI[x].w, 0x01010101, s, false);
-                    rsum[x] = s;
-                }
-            }
-#pragma unroll
-            for (int y = 0; y < WT; ++y) {
-                const int c = jc0 + wc * WT + y;
-                u32x4 p;
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    const int tau = 16 * g + 8 * i + m;
-                    const i32x2 v = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
-                        (lds_i32x2 *)(buf + tau * ROWB + 16 * (c ^ (tau & SWZ)) + 8 * h));
-                    p[2 * i] = (uint32_t)v.x;
-                    p[2 * i + 1] = (uint32_t)v.y;
-                }
-                const u32x4 im = (p << 4) & 0xF0F0F0F0u;
-                const i32x4 reJ = (i32x4)(p & 0xF0F0F0F0u);
-                const i32x4 imJ = (i32x4)im;
-                const i32x4 niJ = (i32x4)(im ^ 0xF0F0F0F0u);
-#pragma unroll
-                for (int x = 0; x < WT; ++x) {
-                    accR[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(reI[x], reJ, accR[x][y], 0, 0, 0);
-                    accI[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(reI[x], niJ, accI[x][y], 0, 0, 0);
-                    accR[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(imI[x], imJ, accR[x][y], 0, 0, 0);
-                    accI[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(imI[x], reJ, accI[x][y], 0, 0, 0);
-                }
-            }
-        }
-    }
-
-    // ---- row sums S_i of the I block (16 * S_i)
-    if (wc == 0) {
-#pragma unroll
-        for (int x = 0; x < WT; ++x) {
-            int s = rsum[x];
-            s += __shfl_xor(s, 16);
-            s += __shfl_xor(s, 32);
-            if (lane < 16) srow[wr * HB + 16 * x + lane] = s;
-        }
-    }
-    __syncthreads();
-    if (!active) return;
-
-    // ---- flush (16x16 MFMA result: lane holds column lane & 15 of rows 4 (lane >> 4) + r)
-    const int kg = lane >> 4, lr = lane & 15;
-    const int64_t tri = (int64_t)N * (N + 1) / 2;
-    int2 *vis = (int2 *)a.vis + (size_t)f * (size_t)tri;
-#pragma unroll
-    for (int x = 0; x < WT; ++x)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int rl = wr * HB + 16 * x + 4 * kg + r;
-            const int i = I0 + rl;
-            if (i >= N) continue;
-            const int32_t scorr = srow[rl] >> 4;
-            const int64_t rowbase = (int64_t)i * (i + 1) / 2;
-#pragma unroll
-            for (int y = 0; y < WT; ++y) {
-                const int j = J0 + wc * HB + 16 * y + lr;
-                if (j > i) continue;
-                const int32_t re = accR[x][y][r] >> 8;
-                const int32_t im = (accI[x][y][r] >> 8) + scorr;
-                int2 *p = vis + rowbase + j;
-                if (a.accumulate) {
-                    int2 o = *p;
-                    o.x += re;
-                    o.y += im;
-                    *p = o;
-                } else {
-                    *p = make_int2(re, im);
-                }
-            }
-        }
-}
 
 } // namespace xeng

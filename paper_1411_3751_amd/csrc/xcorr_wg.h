@@ -1,0 +1,449 @@
+// Persistent-workgroup X-engine kernel for 4-bit input (N a multiple of 16).
+//
+// Work is a host-built list of 128 x 128 tiles (subarray, channel, 128-input
+// block I, block J <= I) of the lower block triangle of
+// V[f] = sum_t x(t, f) x(t, f)^H (Section 2.5; Fig. 2 caption). One
+// workgroup of 4 waves runs per CU and walks its own slice of the list.
+//
+// Staging: each stage of TK = 64 time samples of a tile is copied raw
+// ([time][128 I inputs | 128 J inputs], one byte per complex sample) from
+// HBM into an NBUF-deep LDS ring by buffer loads that write LDS directly,
+// issued NBUF - 1 stages ahead. A stage is published to the four waves by
+// one barrier after each wave's own copies have landed.
+//
+// Fragments: ds_read_b64_tr_b8 turns the time-major rows into the K-major
+// operands of v_mfma_i32_32x32x32_i8 (lane l: input l % 32, K group l / 32).
+// Within each group of 16 lanes, lane 2m + h names time row m of half h of
+// a 16-input chunk and lane 8h + j receives input 8h + j at 8 times.
+//
+// Bank layout: chunk c (16 inputs) of time row tau sits in 16-byte slot
+// c ^ (tau & 7) ^ (8 (c & 1)) of the 256-byte row, so the 8 rows a group
+// reads, and the odd/even chunk pairs two neighbouring groups read, hit
+// distinct banks.
+//
+// Each wave computes a 64 x 64 quarter of the tile as 2 x 2 MFMA tiles of
+// 32 x 32. On a diagonal tile (J = I, only the I half is copied) three
+// quarters are needed: waves 0, 1 take the diagonal ones, wave 2 the lower
+// one, and wave 3 repeats wave 2's work without writing it (every wave runs
+// the same branch-free stage loop).
+//
+// Per stage a wave waits + barriers for the next stage, reads its raw
+// fragments, and issues its MFMAs while the next K step's operands are
+// unpacked (16*re, 16*im, 16*~im, see xcorr_i8.h). Results go to the raw
+// accumulator (Im holds Im V_ij - S_i; the dump subtracts the diagonal).
+#pragma once
+
+#include <type_traits>
+
+#include "xcorr_i8.h"
+
+namespace xeng {
+
+constexpr int WG_ROWB = 256;                   // bytes per staged time row
+constexpr int WG_STAGE = TK * WG_ROWB;         // 16 KB
+constexpr int WG_DMA = WG_STAGE / (WG_THREADS * 16); // 16-byte copies per thread per stage (4)
+constexpr int WG_MAX_SUBS = 16;
+
+typedef int32_t i32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+struct WgSub {
+    const uint8_t *samples; // [T][F][N] packed 4+4-bit
+    int32_t *acc;           // [F][tri(N)][2] raw accumulator
+    int64_t t_begin;        // first sample of this launch's segment
+    int32_t t_count;        // samples in this segment (<= SEG_T), > 0
+    int32_t n_chans;
+    int32_t n_inputs;       // multiple of 16
+    int32_t accumulate;     // 0: overwrite, 1: add
+};
+
+// Tile: chan | sub << 24, then bi | bj << 16 (128-input block indices).
+struct WgItem {
+    uint32_t cs;
+    uint32_t ij;
+};
+
+struct WgArgs {
+    WgSub subs[WG_MAX_SUBS];     // by value in the kernel arguments
+    const WgItem *items;
+    const int32_t *wg_begin;     // [n_wg + 1] item ranges per workgroup
+};
+
+__device__ __forceinline__ int wg_slot(int tau, int c) { return c ^ (tau & 7) ^ ((c & 1) << 3); }
+
+// chunk stored in slot `slot` of row tau (inverse of wg_slot)
+__device__ __forceinline__ int wg_chunk(int tau, int slot)
+{
+    int c = slot ^ (tau & 7);
+    return (c & 1) ? (c ^ 8) : c;
+}
+
+// Wait until at most 4 * n of this wave's copies are outstanding, then barrier.
+__device__ __forceinline__ void wg_wait_barrier(int n)
+{
+    switch (n) {
+    case 0: asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory"); break;
+    case 1: asm volatile("s_waitcnt vmcnt(4)\n\ts_barrier" ::: "memory"); break;
+    case 2: asm volatile("s_waitcnt vmcnt(8)\n\ts_barrier" ::: "memory"); break;
+    case 3: asm volatile("s_waitcnt vmcnt(12)\n\ts_barrier" ::: "memory"); break;
+    case 4: asm volatile("s_waitcnt vmcnt(16)\n\ts_barrier" ::: "memory"); break;
+    case 5: asm volatile("s_waitcnt vmcnt(20)\n\ts_barrier" ::: "memory"); break;
+    default: asm volatile("s_waitcnt vmcnt(24)\n\ts_barrier" ::: "memory"); break;
+    }
+}
+
+// Raw fragments of one stage: [K step][side I/J][32-input block][load]
+typedef i32x2 WgRaw[2][2][2][2];
+
+// MFMA operands of one K step (32 samples)
+struct WgOps {
+    i32x4 reI[2], imI[2], reJ[2], imJ[2], niJ[2];
+};
+
+__device__ __forceinline__ u32x4 wg_raw(const WgRaw &R, int k, int sd, int blk)
+{
+    return u32x4{(uint32_t)R[k][sd][blk][0].x, (uint32_t)R[k][sd][blk][0].y,
+                 (uint32_t)R[k][sd][blk][1].x, (uint32_t)R[k][sd][blk][1].y};
+}
+
+__device__ __forceinline__ void wg_unpack(const WgRaw &R, int k, WgOps &o)
+{
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+        const u32x4 p = wg_raw(R, k, 0, x);
+        o.reI[x] = (i32x4)(p & 0xF0F0F0F0u);
+        o.imI[x] = (i32x4)((p << 4) & 0xF0F0F0F0u);
+    }
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+        const u32x4 p = wg_raw(R, k, 1, y);
+        const u32x4 im = (p << 4) & 0xF0F0F0F0u;
+        o.reJ[y] = (i32x4)(p & 0xF0F0F0F0u);
+        o.imJ[y] = (i32x4)im;
+        o.niJ[y] = (i32x4)(im ^ 0xF0F0F0F0u);
+    }
+}
+
+// 16 v_mfma_i32_32x32x32_i8 of one K step over 2 x 2 tiles of 32 x 32:
+//   accR[x][y] += re_I re_J + im_I im_J,  accI[x][y] += re_I ~im_J + im_I re_J.
+__device__ __forceinline__ void wg_mfma(const WgOps &o, i32x16 (&accR)[2][2], i32x16 (&accI)[2][2])
+{
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            accR[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.reI[x], o.reJ[y], accR[x][y], 0, 0, 0);
+            accI[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.reI[x], o.niJ[y], accI[x][y], 0, 0, 0);
+            accR[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.imI[x], o.imJ[y], accR[x][y], 0, 0, 0);
+            accI[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.imI[x], o.reJ[y], accI[x][y], 0, 0, 0);
+        }
+}
+
+// OCC workgroups per CU: OCC = 1 keeps an 8-deep ring and software-pipelines
+// the next stage's fragment reads and unpack under this stage's MFMAs;
+// OCC = 2 halves the ring and the registers so that two workgroups share a
+// CU and each one's barrier and LDS latency is covered by the other's MFMAs.
+template <int OCC>
+__global__ __launch_bounds__(WG_THREADS, OCC) void xcorr4_wg_kernel(WgArgs a)
+{
+    constexpr int WG_NBUF = OCC == 1 ? 8 : 4;   // LDS ring depth (stages)
+    __shared__ __attribute__((aligned(16))) uint8_t lds[WG_NBUF * WG_STAGE];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    // wave-uniform values go through readfirstlane so that the item and
+    // descriptor loads are scalar loads (a vector load would make the
+    // compiler wait for all vector memory traffic, draining the copy ring)
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    typedef __attribute__((address_space(4))) const uint32_t c_u32_t;
+    typedef __attribute__((address_space(4))) const int32_t c_i32_t;
+    c_u32_t *itw = (c_u32_t *)a.items;
+    c_i32_t *wbeg = (c_i32_t *)a.wg_begin;
+    const int it_begin = __builtin_amdgcn_readfirstlane(wbeg[blockIdx.x]);
+    const int it_end = __builtin_amdgcn_readfirstlane(wbeg[blockIdx.x + 1]);
+    if (it_begin >= it_end) return; // the same for every wave of the workgroup
+    auto item_at = [&](int it) {
+        const int u = __builtin_amdgcn_readfirstlane(it);
+        WgItem w;
+        w.cs = itw[2 * u];
+        w.ij = itw[2 * u + 1];
+        return w;
+    };
+    const uint32_t lds_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)lds;
+    constexpr uint32_t OOR = 0x80000000u;
+
+    // ---- copy cursor (every thread follows the same sequence of stages)
+    int d_item = it_begin, d_stage = 0, d_nstage = 0, d_tcount = 0;
+    const uint8_t *d_base = nullptr;
+    uint32_t d_rowstride = 0;
+    uint32_t d_voff[WG_DMA];
+    auto d_setup = [&](int it) {
+        const WgItem w = item_at(it);
+        const WgSub &sb = a.subs[w.cs >> 24];
+        const int f = (int)(w.cs & 0xFFFFFFu);
+        const int bi = (int)(w.ij & 0xFFFFu), bj = (int)(w.ij >> 16);
+        const int N = sb.n_inputs;
+        d_rowstride = (uint32_t)sb.n_chans * (uint32_t)N;
+        d_tcount = sb.t_count;
+        d_nstage = (sb.t_count + TK - 1) / TK;
+        d_base = sb.samples + ((size_t)sb.t_begin * sb.n_chans + f) * (size_t)N;
+        const bool diag = bi == bj;
+#pragma unroll
+        for (int k = 0; k < WG_DMA; ++k) {
+            const int P = k * WG_THREADS + tid;  // 16-byte position in the stage
+            const int tau = P >> 4, slot = P & 15;
+            const int c = wg_chunk(tau, slot);
+            const int in = c < 8 ? 128 * bi + 16 * c : 128 * bj + 16 * (c - 8);
+            // a diagonal tile reads its J operands from the I half
+            const bool on = in < N && !(diag && c >= 8);
+            d_voff[k] = on ? (uint32_t)tau * d_rowstride + (uint32_t)in : OOR;
+        }
+    };
+    int issued = 0;
+    auto d_issue = [&]() {
+        const int t_first = d_stage * TK;
+        const int nt = d_tcount - t_first < TK ? d_tcount - t_first : TK;
+        const uint64_t base = (uint64_t)(uintptr_t)(d_base + (size_t)t_first * d_rowstride);
+        const i32x4 rsrc = {(int)(uint32_t)base, (int)((uint32_t)(base >> 32) & 0xFFFFu),
+                            (int)((uint32_t)nt * d_rowstride), 0x00020000};
+        const uint32_t dst = lds_base + (uint32_t)((issued % WG_NBUF) * WG_STAGE + wave * 1024);
+#pragma unroll
+        for (int k = 0; k < WG_DMA; ++k)
+            dma16(rsrc, d_voff[k], dst + (uint32_t)(k * WG_THREADS * 16));
+        ++issued;
+        if (++d_stage == d_nstage) {
+            d_stage = 0;
+            if (++d_item < it_end) d_setup(d_item);
+        }
+    };
+
+    int n_total = 0;
+    for (int it = it_begin; it < it_end; ++it) {
+        const WgSub &sb = a.subs[item_at(it).cs >> 24];
+        n_total += (sb.t_count + TK - 1) / TK;
+    }
+    d_setup(it_begin);
+#pragma unroll
+    for (int k = 0; k < WG_NBUF - 1; ++k)
+        if (issued < n_total) d_issue();
+
+    // This wave's 64 x 64 quarter of tile w: I chunks ic.., J chunks jc.. of
+    // the staged row, output origin (r0, c0). On a diagonal tile the J half
+    // is not copied (J = I): waves 0, 1 take the diagonal quarters, wave 2
+    // the lower off-diagonal quarter, and wave 3 repeats wave 2's work
+    // without writing it.
+    auto role = [&](const WgItem &w, int &ic, int &jc, int &r0, int &c0, bool &write) {
+        const int bi = (int)(w.ij & 0xFFFFu), bj = (int)(w.ij >> 16);
+        const int I0 = 128 * bi, J0 = 128 * bj;
+        write = true;
+        if (bi != bj) {
+            const int wr = wave >> 1, wc = wave & 1;
+            ic = 4 * wr;
+            jc = 8 + 4 * wc;
+            r0 = I0 + 64 * wr;
+            c0 = J0 + 64 * wc;
+        } else if (wave < 2) {
+            ic = jc = 4 * wave;
+            r0 = c0 = I0 + 64 * wave;
+        } else {
+            ic = 4;
+            jc = 0;
+            r0 = I0 + 64;
+            c0 = I0;
+            write = wave == 2;
+        }
+    };
+
+    // ---- read cursor: the stage whose fragments are read next, and the
+    // transpose-load offsets of its tile's role
+    const int G = lane >> 4, m = (lane >> 1) & 7, h = lane & 1;
+    int fo[2][2][2][2]; // (K step, side, block, load) -> byte offset in a stage
+    int r_item = it_begin, r_stage = 0, r_nstage = 0, r_tcount = 0;
+    auto r_setup = [&](int it) {
+        const WgItem w = item_at(it);
+        const WgSub &sb = a.subs[w.cs >> 24];
+        r_tcount = sb.t_count;
+        r_nstage = (sb.t_count + TK - 1) / TK;
+        int ic, jc, r0, c0;
+        bool write;
+        role(w, ic, jc, r0, c0, write);
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+                for (int blk = 0; blk < 2; ++blk)
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        const int tau = 32 * k + 16 * (G >> 1) + 8 * i + m;
+                        const int c = (sd == 0 ? ic : jc) + 2 * blk + (G & 1);
+                        fo[k][sd][blk][i] = tau * WG_ROWB + 16 * wg_slot(tau, c) + 8 * h;
+                    }
+    };
+
+    // Make the read cursor's stage s visible to every wave: this wave's
+    // copies of it are done once at most the later issued stages are
+    // outstanding; then barrier. Rows past the end of the segment are
+    // cleared cooperatively. Advances the read cursor.
+    auto prep_stage = [&](int s) {
+        const int later = issued - (s + 1);
+        if (later >= WG_NBUF - 2) wg_wait_barrier(WG_NBUF - 2);
+        else if (later >= 1) wg_wait_barrier(1);
+        else wg_wait_barrier(0);
+        const int nt = r_tcount - r_stage * TK;
+        if (nt < TK) {
+            uint8_t *b = lds + (s % WG_NBUF) * WG_STAGE;
+            for (int o = tid * 16; o < WG_STAGE; o += WG_THREADS * 16)
+                if (o / WG_ROWB >= nt) *(u32x4 *)(b + o) = u32x4{0u, 0u, 0u, 0u};
+            asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        }
+    };
+    auto r_advance = [&]() {
+        if (++r_stage == r_nstage) {
+            r_stage = 0;
+            if (++r_item < it_end) r_setup(r_item);
+        }
+    };
+    auto read_frags = [&](int slot, WgRaw &R) {
+        const uint8_t *b = lds + slot * WG_STAGE;
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+                for (int blk = 0; blk < 2; ++blk)
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+                        R[k][sd][blk][i] = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
+                            (lds_i32x2 *)(b + fo[k][sd][blk][i]));
+    };
+
+    i32x16 accR[2][2], accI[2][2];
+    WgRaw RA, RB;
+    WgOps O0, O1;
+    r_setup(it_begin);
+    prep_stage(0);
+    read_frags(0, RA);
+    r_advance();
+    wg_unpack(RA, 0, O0);
+    int s = 0; // global index of the stage being multiplied
+
+    for (int it = it_begin; it < it_end; ++it) {
+        const WgItem w = item_at(it);
+        const WgSub &sb = a.subs[w.cs >> 24];
+        const int f = (int)(w.cs & 0xFFFFFFu);
+        const int nst = (sb.t_count + TK - 1) / TK;
+        int ic, jc, r0, c0;
+        bool write;
+        role(w, ic, jc, r0, c0, write);
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                accR[x][y] = i32x16{};
+                accI[x][y] = i32x16{};
+            }
+        if (OCC == 1) {
+            for (int k = 0; k < nst; ++k, ++s) {
+                if (issued < n_total) d_issue();
+                if (s + 1 < n_total) prep_stage(s + 1);
+                // one basic block: read the next stage's fragments (after the
+                // last stage they are stale and unused) and interleave each K
+                // step's MFMAs with the unpack of the next K step
+                read_frags((s + 1) % WG_NBUF, RB);
+                wg_unpack(RA, 1, O1);
+                wg_mfma(O0, accR, accI);
+                wg_unpack(RB, 0, O0);
+                wg_mfma(O1, accR, accI);
+#pragma unroll
+                for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+                    for (int blk = 0; blk < 2; ++blk)
+#pragma unroll
+                        for (int i = 0; i < 2; ++i) RA[1][sd][blk][i] = RB[1][sd][blk][i];
+                __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);
+#pragma unroll
+                for (int q = 0; q < 32; ++q) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+                }
+                if (s + 1 < n_total) r_advance();
+            }
+        } else {
+            // the stage's fragments were read by the previous step (RA); unpack
+            // and multiply one K step at a time, then publish and read the next
+            for (int k = 0; k < nst; ++k, ++s) {
+                if (issued < n_total) d_issue();
+                wg_unpack(RA, 0, O0);
+                wg_mfma(O0, accR, accI);
+                wg_unpack(RA, 1, O0);
+                wg_mfma(O0, accR, accI);
+                if (s + 1 < n_total) {
+                    prep_stage(s + 1);
+                    read_frags((s + 1) % WG_NBUF, RA);
+                    r_advance();
+                }
+            }
+        }
+
+        // ---- flush. 32 x 32 MFMA result: lane l holds column l % 32 of rows
+        // 8 (r / 4) + 4 (l / 32) + r % 4. Buffer loads / stores relative to
+        // row r0: elements above the diagonal, past N, or of a wave that
+        // writes nothing get an out-of-range offset (loads read 0, stores are
+        // dropped), no branches.
+        const int N = sb.n_inputs;
+        const int lh = lane >> 5, lc = lane & 31;
+        const int64_t tri = (int64_t)N * (N + 1) / 2;
+        const int r1 = r0 + 64 < N ? r0 + 64 : (r0 < N ? N : r0);
+        const int64_t rb0 = (int64_t)r0 * (r0 + 1) / 2;
+        const int64_t rb1 = (int64_t)r1 * (r1 + 1) / 2;
+        const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)((uint2 *)sb.acc + (size_t)f * (size_t)tri + (size_t)rb0), (short)0,
+            (int)((rb1 - rb0) * 8), 0x00020000);
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint32_t off[4][2];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int i = r0 + 32 * x + 8 * q + 4 * lh + e;
+                    const int rel = (int)((int64_t)i * (i + 1) / 2 - rb0);
+#pragma unroll
+                    for (int y = 0; y < 2; ++y) {
+                        const int j = c0 + 32 * y + lc;
+                        off[e][y] = (write && i < N && j <= i) ? (uint32_t)(rel + j) * 8u : OOR;
+                    }
+                }
+                if (sb.accumulate) {
+                    u32x2 old[4][2];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+#pragma unroll
+                        for (int y = 0; y < 2; ++y)
+                            old[e][y] = __builtin_amdgcn_raw_buffer_load_b64(vrs, (int)off[e][y], 0, 0);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+#pragma unroll
+                        for (int y = 0; y < 2; ++y) {
+                            const u32x2 v = {old[e][y].x + (uint32_t)(accR[x][y][4 * q + e] >> 8),
+                                             old[e][y].y + (uint32_t)(accI[x][y][4 * q + e] >> 8)};
+                            __builtin_amdgcn_raw_buffer_store_b64(v, vrs, (int)off[e][y], 0, 0);
+                        }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+#pragma unroll
+                        for (int y = 0; y < 2; ++y) {
+                            const u32x2 v = {(uint32_t)(accR[x][y][4 * q + e] >> 8),
+                                             (uint32_t)(accI[x][y][4 * q + e] >> 8)};
+                            __builtin_amdgcn_raw_buffer_store_b64(v, vrs, (int)off[e][y], 0, 0);
+                        }
+                }
+            }
+        // drain the flush (stores may complete out of order with the copies)
+        dma_wait<0>();
+    }
+}
+
+} // namespace xeng

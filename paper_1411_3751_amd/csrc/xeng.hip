@@ -1,9 +1,14 @@
 // libxeng.so: host side of the X-engine C ABI declared in include/xeng.h.
 //
-// Owns the per-subarray int32 accumulators (already in the packed output
-// layout, so a dump is a plain copy), checks the exactness bounds before any
-// launch, splits each call into segments of at most SEG_T samples and
-// launches the tile kernels on the context's stream.
+// Owns the per-subarray int32 accumulators (packed lower triangle; the
+// imaginary words hold Im V_ij - S_i, see xcorr_wg.h, and the dump kernel
+// turns them into Im V_ij), checks the exactness bounds before any launch,
+// splits each call into segments of at most SEG_T samples, and launches:
+//   - 4-bit subarrays with N a multiple of 16: the persistent-workgroup
+//     kernel, all such subarrays of the context in one launch over a
+//     precomputed, cost-balanced list of 128 x 128 tiles;
+//   - other subarrays (8-bit input, other N): the register-staging tile
+//     kernel, one launch per subarray and segment.
 #include <hip/hip_runtime.h>
 
 #include <stdarg.h>
@@ -11,12 +16,15 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
+#include <numeric>
 #include <string>
 #include <vector>
 
 #include "../../include/xeng.h"
 #include "xcorr_i8.h"
+#include "xcorr_wg.h"
 
 namespace {
 
@@ -42,24 +50,45 @@ int fail(int code, const char *fmt, ...)
                         __FILE__, __LINE__);                                           \
     } while (0)
 
+constexpr int MAX_SUBS = 16;        // subarrays per context (kernel-argument descriptors)
+#ifndef WG_OCC
+#define WG_OCC 2                    // workgroups per CU of the persistent kernel
+#endif
+
 struct Sub {
     xeng_subarray cfg{};
-    int32_t *d_acc = nullptr;  // [F][tri][2]
+    int32_t *d_acc = nullptr;  // [F][tri][2], raw convention
     int64_t tri = 0;
     int64_t since_dump = 0;    // samples accumulated since the last reset
     int64_t max_dump = 0;      // exactness bound on since_dump
     bool acc_zero = true;      // accumulator logically zero (next launch overwrites)
-    int wt = 4;                // wave tile edge in 16-row sub-blocks
-    int bt = 128;              // workgroup tile edge
-    int n_tiles = 0;
+    bool wave = false;         // handled by the persistent-workgroup kernel
+    int wt = 4;                // register kernel: wave tile edge in 16-row sub-blocks
+    int bt = 128;              // register kernel: workgroup tile edge
+    int n_tiles = 0;           // register kernel: tiles per channel
+};
+
+// One persistent-kernel launch group: the subarrays it covers and its schedule.
+struct WavePlan {
+    std::vector<int> subs;           // context subarray indices, in launch order
+    std::vector<xeng::WgItem> items; // flat, grouped per workgroup
+    std::vector<int32_t> wg_begin;   // [n_wg + 1]
+    int n_wg = 0;
+    xeng::WgItem *d_items = nullptr;
+    int32_t *d_wg_begin = nullptr;
+    double max_wg_cost = 0, mean_wg_cost = 0;
 };
 
 } // namespace
 
 struct xeng_ctx {
     std::vector<Sub> subs;
+    std::vector<WavePlan> plans;
     hipStream_t stream = nullptr;
     int device = 0;
+    int n_cu = 0;
+    uint32_t *d_stage = nullptr;  // device staging for host dumps
+    size_t stage_words = 0;
 };
 
 namespace {
@@ -74,27 +103,16 @@ KernelFn pick_wt(int wt)
     return xeng::xcorr_i8_kernel<IN_BITS, 4, AL>;
 }
 
-constexpr int DMA_NBUF = 4; // LDS ring depth of the direct-staging kernel
-
-// 4-bit input whose rows split into whole 16-byte chunks takes the
-// direct-staging kernel; everything else the register-staging kernel (whole
-// dword loads when a dword holds whole inputs, else byte loads).
-bool use_dma(int in_bits, int n_inputs) { return in_bits == 4 && n_inputs % 16 == 0; }
-
+// Register-staging kernel: whole dword loads when a dword holds whole inputs.
 KernelFn pick_kernel(int in_bits, int wt, int n_inputs)
 {
-    if (use_dma(in_bits, n_inputs)) {
-        if (wt == 1) return xeng::xcorr4_dma_kernel<1, DMA_NBUF>;
-        if (wt == 2) return xeng::xcorr4_dma_kernel<2, DMA_NBUF>;
-        return xeng::xcorr4_dma_kernel<4, DMA_NBUF>;
-    }
     if (in_bits == 4)
         return (n_inputs % 4 == 0) ? pick_wt<4, true>(wt) : pick_wt<4, false>(wt);
     return (n_inputs % 2 == 0) ? pick_wt<8, true>(wt) : pick_wt<8, false>(wt);
 }
 
-// Tile edge per input count: the smallest workgroup tile that covers N, up
-// to 128 inputs per side.
+bool wave_path(const xeng_subarray &c) { return c.in_bits == 4 && c.n_inputs % 16 == 0; }
+
 int choose_wt(int n_inputs)
 {
     if (n_inputs <= 32) return 1;
@@ -106,8 +124,8 @@ int validate(const xeng_subarray &s, int idx)
 {
     if (s.n_inputs < 1 || s.n_inputs > 65536)
         return fail(XENG_EINVAL, "subarray %d: n_inputs %d out of [1, 65536]", idx, s.n_inputs);
-    if (s.n_chans < 1)
-        return fail(XENG_EINVAL, "subarray %d: n_chans %d < 1", idx, s.n_chans);
+    if (s.n_chans < 1 || s.n_chans > (1 << 24) - 1)
+        return fail(XENG_EINVAL, "subarray %d: n_chans %d out of [1, 2^24)", idx, s.n_chans);
     if (s.n_time < 1)
         return fail(XENG_EINVAL, "subarray %d: n_time %d < 1", idx, s.n_time);
     if (s.in_bits != 4 && s.in_bits != 8)
@@ -116,17 +134,11 @@ int validate(const xeng_subarray &s, int idx)
         return fail(XENG_EINVAL, "subarray %d: unknown engine %d", idx, s.engine);
     if (s.engine == XENG_ENGINE_FP8)
         return fail(XENG_EINVAL, "subarray %d: the FP8 engine is not available in this build", idx);
-    if (s.engine == XENG_ENGINE_FP8 && s.in_bits != 4)
-        return fail(XENG_EINVAL, "subarray %d: the FP8 engine takes 4-bit input only", idx);
-    if (s.engine == XENG_ENGINE_FP8 && s.n_time > XENG_MAX_CALL_SAMPLES_FP8)
-        return fail(XENG_EINVAL, "subarray %d: n_time %d above the FP8 per-call limit %lld", idx,
-                    s.n_time, (long long)XENG_MAX_CALL_SAMPLES_FP8);
     const int64_t tri = (int64_t)s.n_inputs * (s.n_inputs + 1) / 2;
-    const int64_t nb = (s.n_inputs + 127) / 128;
-    if (tri * (int64_t)s.n_chans * 2 > ((int64_t)1 << 40) || nb * (nb + 1) / 2 * s.n_chans > INT32_MAX)
+    if (tri * (int64_t)s.n_chans * 2 > ((int64_t)1 << 40))
         return fail(XENG_EINVAL, "subarray %d: output too large", idx);
-    // one LDS stage of the tile kernel spans TK time rows of the whole
-    // [F][N] plane; its byte offsets must fit the 32-bit buffer offsets
+    // one stage spans TK time rows of the whole [F][N] plane; its byte
+    // offsets must fit the 32-bit buffer offsets
     if ((int64_t)s.n_chans * s.n_inputs * (s.in_bits / 4) * xeng::TK >= ((int64_t)1 << 31))
         return fail(XENG_EINVAL, "subarray %d: n_chans * n_inputs too large for one stream", idx);
     const int64_t bound = s.in_bits == 4 ? XENG_MAX_DUMP_SAMPLES_4BIT : XENG_MAX_DUMP_SAMPLES_8BIT;
@@ -136,19 +148,109 @@ int validate(const xeng_subarray &s, int idx)
     return XENG_OK;
 }
 
-int zero_device(int32_t *p, size_t n_words, hipStream_t st)
+// ---- schedule of the persistent-workgroup kernel ------------------------
+//
+// Tiles (subarray, channel, 128-input block I, block J <= I) are listed in
+// locality order (subarray, channel, I, J). The list is cut into 8
+// contiguous parts of equal cost, one per XCD (workgroup b runs on XCD
+// b mod 8). Within an XCD the tiles are dealt out in rounds of one tile per
+// workgroup, so that the workgroups of an XCD work on neighbouring tiles (the
+// same channels, at the same times, whose rows they share in that XCD's L2);
+// inside a round the costliest tile goes to the least-loaded workgroup.
+void build_schedule(WavePlan &p, const std::vector<Sub> &subs, int n_cu)
+{
+    struct It {
+        xeng::WgItem w;
+        double cost;
+    };
+    std::vector<It> all;
+    for (size_t k = 0; k < p.subs.size(); ++k) {
+        const Sub &s = subs[p.subs[k]];
+        const int nb = (s.cfg.n_inputs + 127) / 128;
+        const int nst = (s.cfg.n_time + xeng::TK - 1) / xeng::TK;
+        const int segs = (s.cfg.n_time + xeng::SEG_T - 1) / xeng::SEG_T;
+        const double per_stage = (double)nst / segs;
+        for (int f = 0; f < s.cfg.n_chans; ++f)
+            for (int bi = 0; bi < nb; ++bi)
+                for (int bj = 0; bj <= bi; ++bj) {
+                    It it;
+                    it.w.cs = (uint32_t)f | ((uint32_t)k << 24);
+                    it.w.ij = (uint32_t)bi | ((uint32_t)bj << 16);
+                    // every tile takes one stage loop per stage (a diagonal
+                    // tile keeps all 4 waves busy too), plus a per-tile flush
+                    it.cost = per_stage + 2.0;
+                    all.push_back(it);
+                }
+    }
+    const int64_t n_items = (int64_t)all.size();
+    const int n_wg = (int)std::min<int64_t>((int64_t)n_cu * WG_OCC, n_items);
+    p.n_wg = n_wg;
+    std::vector<std::vector<int>> xwg(8);
+    for (int b = 0; b < n_wg; ++b) xwg[b % 8].push_back(b);
+    const double total = std::accumulate(all.begin(), all.end(), 0.0,
+                                         [](double acc, const It &i) { return acc + i.cost; });
+    std::vector<std::vector<xeng::WgItem>> per_wg(n_wg);
+    std::vector<double> load(n_wg, 0.0);
+    int64_t pos = 0;
+    double cum = 0.0, cum_target = 0.0;
+    for (int x = 0; x < 8; ++x) {
+        if (xwg[x].empty()) continue;
+        cum_target += total * (double)xwg[x].size() / (double)n_wg;
+        const int64_t first = pos;
+        while (pos < n_items && (x == 7 || cum + all[pos].cost * 0.5 <= cum_target)) {
+            cum += all[pos].cost;
+            ++pos;
+        }
+        const std::vector<int> &ws = xwg[x];
+        for (int64_t r0 = first; r0 < pos; r0 += (int64_t)ws.size()) {
+            const int64_t r1 = std::min<int64_t>(pos, r0 + (int64_t)ws.size());
+            std::vector<int64_t> idx(r1 - r0);
+            std::iota(idx.begin(), idx.end(), r0);
+            std::stable_sort(idx.begin(), idx.end(),
+                             [&](int64_t a, int64_t b) { return all[a].cost > all[b].cost; });
+            std::vector<int> wv(ws);
+            std::stable_sort(wv.begin(), wv.end(), [&](int a, int b) { return load[a] < load[b]; });
+            for (size_t q = 0; q < idx.size(); ++q) {
+                per_wg[wv[q]].push_back(all[idx[q]].w);
+                load[wv[q]] += all[idx[q]].cost;
+            }
+        }
+    }
+    p.items.clear();
+    p.wg_begin.assign(1, 0);
+    for (int b = 0; b < n_wg; ++b) {
+        p.items.insert(p.items.end(), per_wg[b].begin(), per_wg[b].end());
+        p.wg_begin.push_back((int32_t)p.items.size());
+    }
+    p.max_wg_cost = *std::max_element(load.begin(), load.end());
+    p.mean_wg_cost = total / n_wg;
+}
+
+int upload_plan(WavePlan &p)
+{
+    HIP_TRY(hipMalloc((void **)&p.d_items,
+                      sizeof(xeng::WgItem) * std::max<size_t>(1, p.items.size())));
+    HIP_TRY(hipMalloc((void **)&p.d_wg_begin, sizeof(int32_t) * p.wg_begin.size()));
+    HIP_TRY(hipMemcpy(p.d_items, p.items.data(), sizeof(xeng::WgItem) * p.items.size(),
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p.d_wg_begin, p.wg_begin.data(), sizeof(int32_t) * p.wg_begin.size(),
+                      hipMemcpyHostToDevice));
+    return XENG_OK;
+}
+
+int zero_device(uint32_t *p, size_t n_words, hipStream_t st)
 {
     const size_t n16 = n_words / 4, ntail = n_words % 4;
     int blocks = (int)((n16 + 255) / 256);
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(xeng::fill_zero_kernel, dim3(blocks), dim3(256), 0, st, (int4 *)p, n16,
-                       p + n16 * 4, ntail);
+                       (int32_t *)p + n16 * 4, ntail);
     HIP_TRY(hipGetLastError());
     return XENG_OK;
 }
 
-int launch_sub(Sub &s, const void *d_samples, hipStream_t st)
+int launch_regs(Sub &s, const void *d_samples, hipStream_t st)
 {
     const xeng_subarray &c = s.cfg;
     KernelFn fn = pick_kernel(c.in_bits, s.wt, c.n_inputs);
@@ -157,7 +259,7 @@ int launch_sub(Sub &s, const void *d_samples, hipStream_t st)
         a.samples = (const uint8_t *)d_samples;
         a.vis = s.d_acc;
         a.t_begin = t0;
-        a.t_count = (int32_t)((c.n_time - t0) < xeng::SEG_T ? (c.n_time - t0) : xeng::SEG_T);
+        a.t_count = (int32_t)std::min<int64_t>(c.n_time - t0, xeng::SEG_T);
         a.n_chans = c.n_chans;
         a.n_inputs = c.n_inputs;
         a.n_tiles = s.n_tiles;
@@ -168,6 +270,59 @@ int launch_sub(Sub &s, const void *d_samples, hipStream_t st)
         s.acc_zero = false;
     }
     return XENG_OK;
+}
+
+// All subarrays of a plan have the same number of segments (a plan with
+// several subarrays is only built when every one fits in one segment).
+int launch_wave(xeng_ctx *ctx, WavePlan &p, const void *const *d_samples)
+{
+    const Sub &s0 = ctx->subs[p.subs[0]];
+    const int64_t T = s0.cfg.n_time;
+    for (int64_t t0 = 0; t0 < T; t0 += xeng::SEG_T) {
+        xeng::WgArgs a;
+        memset(&a, 0, sizeof a);
+        for (size_t k = 0; k < p.subs.size(); ++k) {
+            Sub &s = ctx->subs[p.subs[k]];
+            xeng::WgSub &w = a.subs[k];
+            w.samples = (const uint8_t *)d_samples[p.subs[k]];
+            w.acc = s.d_acc;
+            w.t_begin = t0;
+            w.t_count = (int32_t)std::min<int64_t>(s.cfg.n_time - t0, xeng::SEG_T);
+            w.n_chans = s.cfg.n_chans;
+            w.n_inputs = s.cfg.n_inputs;
+            w.accumulate = s.acc_zero ? 0 : 1;
+        }
+        a.items = p.d_items;
+        a.wg_begin = p.d_wg_begin;
+        hipLaunchKernelGGL(xeng::xcorr4_wg_kernel<WG_OCC>, dim3(p.n_wg), dim3(xeng::WG_THREADS), 0,
+                           ctx->stream, a);
+        HIP_TRY(hipGetLastError());
+        for (int k : p.subs) ctx->subs[k].acc_zero = false;
+    }
+    return XENG_OK;
+}
+
+int dump_device(const Sub &s, uint32_t *out, hipStream_t st)
+{
+    const int64_t n2 = s.tri * s.cfg.n_chans;
+    int blocks = (int)std::min<int64_t>((n2 + 255) / 256, 16384);
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(xeng::dump_kernel, dim3(blocks), dim3(256), 0, st,
+                       (const uint32_t *)s.d_acc, out, n2, s.tri);
+    HIP_TRY(hipGetLastError());
+    return XENG_OK;
+}
+
+void free_ctx(xeng_ctx *ctx)
+{
+    for (Sub &s : ctx->subs)
+        if (s.d_acc) (void)hipFree(s.d_acc);
+    for (WavePlan &p : ctx->plans) {
+        if (p.d_items) (void)hipFree(p.d_items);
+        if (p.d_wg_begin) (void)hipFree(p.d_wg_begin);
+    }
+    if (ctx->d_stage) (void)hipFree(ctx->d_stage);
+    delete ctx;
 }
 
 } // namespace
@@ -193,7 +348,8 @@ int xeng_create(const xeng_subarray *subs, int n_subs, void *hip_stream, xeng_ct
     if (!out) return fail(XENG_EINVAL, "out is NULL");
     *out = nullptr;
     if (!subs) return fail(XENG_EINVAL, "subs is NULL");
-    if (n_subs < 1 || n_subs > 64) return fail(XENG_EINVAL, "n_subs %d out of [1, 64]", n_subs);
+    if (n_subs < 1 || n_subs > MAX_SUBS)
+        return fail(XENG_EINVAL, "n_subs %d out of [1, %d]", n_subs, MAX_SUBS);
     for (int k = 0; k < n_subs; ++k) {
         int rc = validate(subs[k], k);
         if (rc) return rc;
@@ -201,16 +357,21 @@ int xeng_create(const xeng_subarray *subs, int n_subs, void *hip_stream, xeng_ct
     xeng_ctx *ctx = new (std::nothrow) xeng_ctx;
     if (!ctx) return fail(XENG_ENOMEM, "host allocation failed");
     ctx->stream = (hipStream_t)hip_stream;
-    if (hipGetDevice(&ctx->device) != hipSuccess) {
+    if (hipGetDevice(&ctx->device) != hipSuccess ||
+        hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device) !=
+            hipSuccess ||
+        ctx->n_cu < 1) {
         delete ctx;
-        return fail(XENG_EHIP, "hipGetDevice failed");
+        return fail(XENG_EHIP, "cannot query the current HIP device");
     }
     ctx->subs.resize(n_subs);
+    std::vector<int> wave_subs;
     for (int k = 0; k < n_subs; ++k) {
         Sub &s = ctx->subs[k];
         s.cfg = subs[k];
         s.tri = (int64_t)s.cfg.n_inputs * (s.cfg.n_inputs + 1) / 2;
         s.max_dump = s.cfg.in_bits == 4 ? XENG_MAX_DUMP_SAMPLES_4BIT : XENG_MAX_DUMP_SAMPLES_8BIT;
+        s.wave = wave_path(s.cfg);
         s.wt = choose_wt(s.cfg.n_inputs);
         s.bt = 32 * s.wt;
         const int nb = (s.cfg.n_inputs + s.bt - 1) / s.bt;
@@ -219,11 +380,35 @@ int xeng_create(const xeng_subarray *subs, int n_subs, void *hip_stream, xeng_ct
         hipError_t e = hipMalloc((void **)&s.d_acc, bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            xeng_destroy(ctx);
+            free_ctx(ctx);
             return fail(XENG_ENOMEM, "hipMalloc(%zu) for subarray %d: %s", bytes, k,
                         hipGetErrorString(e));
         }
-        s.acc_zero = true;
+        if (s.wave) wave_subs.push_back(k);
+    }
+    // one launch group for all wave-path subarrays when each fits one
+    // segment; otherwise one group per subarray
+    bool one_group = true;
+    for (int k : wave_subs)
+        if (ctx->subs[k].cfg.n_time > xeng::SEG_T) one_group = false;
+    if (!wave_subs.empty()) {
+        if (one_group) {
+            ctx->plans.emplace_back();
+            ctx->plans.back().subs = wave_subs;
+        } else {
+            for (int k : wave_subs) {
+                ctx->plans.emplace_back();
+                ctx->plans.back().subs = {k};
+            }
+        }
+    }
+    for (WavePlan &p : ctx->plans) {
+        build_schedule(p, ctx->subs, ctx->n_cu);
+        int rc = upload_plan(p);
+        if (rc) {
+            free_ctx(ctx);
+            return rc;
+        }
     }
     *out = ctx;
     return XENG_OK;
@@ -235,9 +420,7 @@ int xeng_destroy(xeng_ctx *ctx)
     int rc = XENG_OK;
     if (hipStreamSynchronize(ctx->stream) != hipSuccess)
         rc = fail(XENG_EHIP, "hipStreamSynchronize failed in destroy");
-    for (Sub &s : ctx->subs)
-        if (s.d_acc) (void)hipFree(s.d_acc);
-    delete ctx;
+    free_ctx(ctx);
     return rc;
 }
 
@@ -256,19 +439,24 @@ int xeng_correlate(xeng_ctx *ctx, const void *const *d_samples)
     for (size_t k = 0; k < ctx->subs.size(); ++k) {
         const Sub &s = ctx->subs[k];
         if (!d_samples[k]) return fail(XENG_EINVAL, "d_samples[%zu] is NULL", k);
-        if (((uintptr_t)d_samples[k] & 3) != 0)
-            return fail(XENG_EINVAL, "d_samples[%zu] is not 4-byte aligned", k);
+        if (((uintptr_t)d_samples[k] & 15) != 0)
+            return fail(XENG_EINVAL, "d_samples[%zu] is not 16-byte aligned", k);
         if (s.since_dump + s.cfg.n_time > s.max_dump)
             return fail(XENG_ERANGE,
                         "subarray %zu: %lld + %d samples since the last dump would exceed the "
                         "exactness bound %lld",
                         k, (long long)s.since_dump, s.cfg.n_time, (long long)s.max_dump);
     }
-    for (size_t k = 0; k < ctx->subs.size(); ++k) {
-        int rc = launch_sub(ctx->subs[k], d_samples[k], ctx->stream);
+    for (WavePlan &p : ctx->plans) {
+        int rc = launch_wave(ctx, p, d_samples);
         if (rc) return rc;
-        ctx->subs[k].since_dump += ctx->subs[k].cfg.n_time;
     }
+    for (size_t k = 0; k < ctx->subs.size(); ++k)
+        if (!ctx->subs[k].wave) {
+            int rc = launch_regs(ctx->subs[k], d_samples[k], ctx->stream);
+            if (rc) return rc;
+        }
+    for (Sub &s : ctx->subs) s.since_dump += s.cfg.n_time;
     return XENG_OK;
 }
 
@@ -279,25 +467,41 @@ int xeng_dump(xeng_ctx *ctx, void *const *out, int out_is_device, int reset)
     if (out)
         for (size_t k = 0; k < ctx->subs.size(); ++k)
             if (!out[k]) return fail(XENG_EINVAL, "out[%zu] is NULL", k);
-    bool host_copy = false;
     for (size_t k = 0; k < ctx->subs.size() && out; ++k) {
         Sub &s = ctx->subs[k];
         const size_t words = (size_t)s.tri * (size_t)s.cfg.n_chans * 2;
         if (s.acc_zero) {
             if (out_is_device) {
-                int rc = zero_device((int32_t *)out[k], words, ctx->stream);
+                int rc = zero_device((uint32_t *)out[k], words, ctx->stream);
                 if (rc) return rc;
             } else {
+                HIP_TRY(hipStreamSynchronize(ctx->stream));
                 memset(out[k], 0, words * 4);
             }
+        } else if (out_is_device) {
+            int rc = dump_device(s, (uint32_t *)out[k], ctx->stream);
+            if (rc) return rc;
         } else {
-            HIP_TRY(hipMemcpyAsync(out[k], s.d_acc, words * 4,
-                                   out_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+            if (ctx->stage_words < words) {
+                HIP_TRY(hipStreamSynchronize(ctx->stream));
+                if (ctx->d_stage) (void)hipFree(ctx->d_stage);
+                ctx->d_stage = nullptr;
+                ctx->stage_words = 0;
+                hipError_t e = hipMalloc((void **)&ctx->d_stage, words * 4);
+                if (e != hipSuccess) {
+                    (void)hipGetLastError();
+                    return fail(XENG_ENOMEM, "hipMalloc(%zu) for the dump staging buffer: %s",
+                                words * 4, hipGetErrorString(e));
+                }
+                ctx->stage_words = words;
+            }
+            int rc = dump_device(s, ctx->d_stage, ctx->stream);
+            if (rc) return rc;
+            HIP_TRY(hipMemcpyAsync(out[k], ctx->d_stage, words * 4, hipMemcpyDeviceToHost,
                                    ctx->stream));
-            host_copy |= !out_is_device;
+            HIP_TRY(hipStreamSynchronize(ctx->stream));
         }
     }
-    if (host_copy) HIP_TRY(hipStreamSynchronize(ctx->stream));
     if (reset)
         for (Sub &s : ctx->subs) {
             s.acc_zero = true;
@@ -309,7 +513,8 @@ int xeng_dump(xeng_ctx *ctx, void *const *out, int out_is_device, int reset)
 int xeng_samples_since_dump(const xeng_ctx *ctx, int sub, int64_t *out)
 {
     if (!ctx || !out) return fail(XENG_EINVAL, "NULL argument");
-    if (sub < 0 || sub >= (int)ctx->subs.size()) return fail(XENG_EINVAL, "sub %d out of range", sub);
+    if (sub < 0 || sub >= (int)ctx->subs.size())
+        return fail(XENG_EINVAL, "sub %d out of range", sub);
     *out = ctx->subs[sub].since_dump;
     return XENG_OK;
 }
@@ -317,7 +522,8 @@ int xeng_samples_since_dump(const xeng_ctx *ctx, int sub, int64_t *out)
 int xeng_max_dump_samples(const xeng_ctx *ctx, int sub, int64_t *out)
 {
     if (!ctx || !out) return fail(XENG_EINVAL, "NULL argument");
-    if (sub < 0 || sub >= (int)ctx->subs.size()) return fail(XENG_EINVAL, "sub %d out of range", sub);
+    if (sub < 0 || sub >= (int)ctx->subs.size())
+        return fail(XENG_EINVAL, "sub %d out of range", sub);
     *out = ctx->subs[sub].max_dump;
     return XENG_OK;
 }
@@ -325,19 +531,37 @@ int xeng_max_dump_samples(const xeng_ctx *ctx, int sub, int64_t *out)
 int xeng_plan_describe(const xeng_ctx *ctx, char *buf, size_t len)
 {
     if (!ctx || !buf) return fail(XENG_EINVAL, "NULL argument");
-    std::string js = "{\"subarrays\": [";
+    std::string js = "{\"compute_units\": " + std::to_string(ctx->n_cu) + ", \"subarrays\": [";
     for (size_t k = 0; k < ctx->subs.size(); ++k) {
         const Sub &s = ctx->subs[k];
-        char item[384];
+        char item[512];
         const int64_t segs = (s.cfg.n_time + xeng::SEG_T - 1) / xeng::SEG_T;
+        if (s.wave)
+            snprintf(item, sizeof item,
+                     "%s{\"n_inputs\": %d, \"n_chans\": %d, \"n_time\": %d, \"in_bits\": %d, "
+                     "\"engine\": \"%s\", \"kernel\": \"persistent_workgroup\", \"tile\": 128, "
+                     "\"launches_per_call\": %lld}",
+                     k ? ", " : "", s.cfg.n_inputs, s.cfg.n_chans, s.cfg.n_time, s.cfg.in_bits,
+                     s.cfg.engine == XENG_ENGINE_I8 ? "i8" : "fp8", (long long)segs);
+        else
+            snprintf(item, sizeof item,
+                     "%s{\"n_inputs\": %d, \"n_chans\": %d, \"n_time\": %d, \"in_bits\": %d, "
+                     "\"engine\": \"%s\", \"kernel\": \"register_staging\", \"tile\": %d, "
+                     "\"wave_tile\": %d, \"tiles_per_chan\": %d, \"workgroups\": %lld, "
+                     "\"launches_per_call\": %lld}",
+                     k ? ", " : "", s.cfg.n_inputs, s.cfg.n_chans, s.cfg.n_time, s.cfg.in_bits,
+                     s.cfg.engine == XENG_ENGINE_I8 ? "i8" : "fp8", s.bt, s.bt / 2, s.n_tiles,
+                     (long long)s.n_tiles * s.cfg.n_chans, (long long)segs);
+        js += item;
+    }
+    js += "], \"persistent_launch_groups\": [";
+    for (size_t q = 0; q < ctx->plans.size(); ++q) {
+        const WavePlan &p = ctx->plans[q];
+        char item[256];
         snprintf(item, sizeof item,
-                 "%s{\"n_inputs\": %d, \"n_chans\": %d, \"n_time\": %d, \"in_bits\": %d, "
-                 "\"engine\": \"%s\", \"staging\": \"%s\", \"tile\": %d, \"wave_tile\": %d, \"tiles_per_chan\": %d, "
-                 "\"workgroups\": %lld, \"launches_per_call\": %lld}",
-                 k ? ", " : "", s.cfg.n_inputs, s.cfg.n_chans, s.cfg.n_time, s.cfg.in_bits,
-                 s.cfg.engine == XENG_ENGINE_I8 ? "i8" : "fp8",
-                 use_dma(s.cfg.in_bits, s.cfg.n_inputs) ? "lds_dma" : "registers", s.bt, s.bt / 2, s.n_tiles,
-                 (long long)s.n_tiles * s.cfg.n_chans, (long long)segs);
+                 "%s{\"subarrays\": %zu, \"items\": %zu, \"workgroups\": %d, \"balance\": %.4f}",
+                 q ? ", " : "", p.subs.size(), p.items.size(), p.n_wg,
+                 p.max_wg_cost > 0 ? p.mean_wg_cost / p.max_wg_cost : 1.0);
         js += item;
     }
     js += "]}";

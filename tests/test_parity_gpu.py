@@ -150,3 +150,33 @@ def test_leda_gulp_sampled_channels(torch_cuda, oracle_lib):
     for f in rng.choice(others, 16, replace=False):
         w = rng.integers(-4, 5, size=(512, 2)).astype(np.int64)
         assert oracle_lib.projection_check(s, 4, int(f), got[f], w) == 0
+
+
+def test_multi_segment_wave_path(torch_cuda, oracle_lib):
+    # N a multiple of 16 (wave-persistent kernel), a call of 3 launch segments
+    print("case multi-segment wave path", flush=True)
+    rng = np.random.default_rng(98)
+    s = rand_stream(rng, 70000, 2, 48, 4)
+    want = oracle_lib.narrow(oracle_lib.correlate(s, 4))
+    assert np.array_equal(gpu_once(torch_cuda, s, 4), want)
+
+
+def test_several_subarrays_one_context(torch_cuda, oracle_lib):
+    # subarrays of uneven shape in one context: wave-path ones share one
+    # persistent launch, the others take the register-staging kernel
+    from paper_1411_3751_amd import Correlator
+    torch = torch_cuda
+    print("case several subarrays", flush=True)
+    rng = np.random.default_rng(77)
+    shapes = [(16, 5, 300, 4), (64, 3, 300, 4), (192, 2, 130, 4), (100, 2, 200, 4), (48, 2, 90, 8)]
+    streams = [rand_stream(rng, T, F, N, b) for (N, F, T, b) in shapes]
+    subs = [dict(n_inputs=N, n_chans=F, n_time=T, in_bits=b) for (N, F, T, b) in shapes]
+    with Correlator(subs) as c:
+        dev = [torch.from_numpy(x).cuda() for x in streams]
+        c.correlate(dev)
+        c.correlate(dev)
+        outs = [o.cpu().numpy() for o in c.dump()]
+    for (N, F, T, b), x, got in zip(shapes, streams, outs):
+        acc = oracle_lib.correlate(x, b)
+        want = oracle_lib.narrow(acc * 2)
+        assert np.array_equal(got, want), (N, F, T, b)
