@@ -71,7 +71,7 @@ typedef struct xeng_ctx xeng_ctx; /* opaque, library-owned */
 
 /* One subarray: an independent set of inputs correlated with its own shape. */
 typedef struct {
-    int32_t n_inputs; /* N >= 1 inputs (input i = 2 * antenna + polarisation) */
+    int32_t n_inputs; /* 1 <= N <= 65535 inputs (input i = 2 * antenna + polarisation) */
     int32_t n_chans;  /* F >= 1 channels */
     int32_t n_time;   /* T >= 1 time samples consumed per xeng_correlate call */
     int32_t in_bits;  /* 4 or 8, see above */
@@ -79,7 +79,7 @@ typedef struct {
 } xeng_subarray;
 
 /*
- * Create a context for n_subs (1..64) subarrays. Allocates the device
+ * Create a context for n_subs (1..16) subarrays. Allocates the device
  * accumulators (n_chans * N(N+1)/2 * 8 bytes each) on the current HIP device
  * and plans the launches. hip_stream is a hipStream_t (NULL = the null
  * stream). On success *out receives the context; on failure *out is NULL and

@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libxeng.so")
 SOURCES = [os.path.join(HERE, "csrc", "xeng.hip")]
-HEADERS = [os.path.join(HERE, "csrc", "xcorr_i8.h"), os.path.join(ROOT, "include", "xeng.h")]
+HEADERS = [os.path.join(HERE, "csrc", "xcorr_i8.h"), os.path.join(HERE, "csrc", "xcorr_wg.h"),
+           os.path.join(ROOT, "include", "xeng.h")]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for all device code (they are not

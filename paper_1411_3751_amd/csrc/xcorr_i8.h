@@ -19,8 +19,9 @@
 //   4. four v_mfma_i32_16x16x64_i8 per 16x16 sub-tile and stage:
 //        accR += (16re_i)(16re_j) + (16im_i)(16im_j)             = 256 Re V
 //        accI += (16re_i)(16(~im_j)) + (16im_i)(16re_j)          = 256 (Im V - S_i)
-//      with S_i = sum_t re_i(t), kept per row with v_dot4 on the unpacked
-//      16*re bytes and added back at the flush.
+//      with S_i = sum_t re_i(t). The accumulator keeps this raw form. Since
+//      Im V_ii = 0, the diagonal cell holds -S_i exactly, and the dump
+//      kernel recovers Im V_ij = raw_ij - raw_ii (mod 2^32, exact).
 // For 8+8-bit input the rows hold int8 re and im separately (no scaling) and
 // the same ~im identity gives accI = Im V - S_i.
 //
@@ -324,20 +325,45 @@ __global__ void fill_zero_kernel(int4 *p, size_t n16, int32_t *tail, size_t ntai
 
 // Dump of a raw accumulator into the output convention: Re unchanged,
 // Im V_ij = raw_ij - raw_ii (the diagonal entry of row i holds -S_i).
-// Arithmetic is modulo 2^32; the true value fits int32. One thread per
-// output word pair, any grid.
-__global__ void dump_kernel(const uint32_t *acc, uint32_t *out, int64_t n_words2, int64_t tri)
+// Arithmetic is modulo 2^32; the true value fits int32.
+//
+// Grid: (ceil(tri / DUMP_PER_WG), channels), starting at channel chan0. Each
+// workgroup converts DUMP_PER_WG consecutive cells of one channel; every load and store
+// instruction of a wave covers 64 consecutive 8-byte cells. The row index of
+// cell k solves i (i + 1) / 2 <= k < (i + 1) (i + 2) / 2: a float square root
+// gives it to within one, and one integer correction each way makes it exact
+// (k < 2^31, so 8k + 1 is off by at most 2^7 in float and its root by less
+// than 2^-8).
+constexpr int DUMP_ITEMS = 8;
+constexpr int DUMP_PER_WG = 256 * DUMP_ITEMS;
+
+__global__ __launch_bounds__(256) void dump_kernel(const uint2 *__restrict__ acc,
+                                                   uint2 *__restrict__ out, int32_t tri,
+                                                   int32_t chan0)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_words2; e += stride) {
-        const int64_t f = e / tri, k = e - f * tri;
-        int64_t i = (int64_t)((__builtin_sqrt(8.0 * (double)k + 1.0) - 1.0) * 0.5);
-        while (i * (i + 1) / 2 > k) --i;
-        while ((i + 1) * (i + 2) / 2 <= k) ++i;
-        const int64_t d = f * tri + i * (i + 1) / 2 + i;
-        const uint2 v = ((const uint2 *)acc)[e];
-        const uint32_t sd = ((const uint32_t *)acc)[2 * d + 1];
-        ((uint2 *)out)[e] = make_uint2(v.x, v.y - sd);
+    const int64_t cbase = (int64_t)(chan0 + blockIdx.y) * tri;
+    const int32_t k0 = blockIdx.x * DUMP_PER_WG + threadIdx.x;
+    uint2 v[DUMP_ITEMS];
+    uint32_t sd[DUMP_ITEMS];
+#pragma unroll
+    for (int r = 0; r < DUMP_ITEMS; ++r) {
+        const int32_t k = k0 + 256 * r;
+        if (k < tri) v[r] = acc[cbase + k];
+    }
+#pragma unroll
+    for (int r = 0; r < DUMP_ITEMS; ++r) {
+        const int32_t k = k0 + 256 * r;
+        if (k < tri) {
+            int64_t i = (int64_t)((__builtin_sqrtf(8.0f * (float)k + 1.0f) - 1.0f) * 0.5f);
+            if (i * (i + 1) / 2 > k) --i;
+            if ((i + 1) * (i + 2) / 2 <= k) ++i;
+            sd[r] = acc[cbase + i * (i + 1) / 2 + i].y;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < DUMP_ITEMS; ++r) {
+        const int32_t k = k0 + 256 * r;
+        if (k < tri) out[cbase + k] = make_uint2(v[r].x, v[r].y - sd[r]);
     }
 }
 

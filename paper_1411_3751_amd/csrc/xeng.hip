@@ -122,8 +122,8 @@ int choose_wt(int n_inputs)
 
 int validate(const xeng_subarray &s, int idx)
 {
-    if (s.n_inputs < 1 || s.n_inputs > 65536)
-        return fail(XENG_EINVAL, "subarray %d: n_inputs %d out of [1, 65536]", idx, s.n_inputs);
+    if (s.n_inputs < 1 || s.n_inputs > 65535)
+        return fail(XENG_EINVAL, "subarray %d: n_inputs %d out of [1, 65535]", idx, s.n_inputs);
     if (s.n_chans < 1 || s.n_chans > (1 << 24) - 1)
         return fail(XENG_EINVAL, "subarray %d: n_chans %d out of [1, 2^24)", idx, s.n_chans);
     if (s.n_time < 1)
@@ -304,12 +304,13 @@ int launch_wave(xeng_ctx *ctx, WavePlan &p, const void *const *d_samples)
 
 int dump_device(const Sub &s, uint32_t *out, hipStream_t st)
 {
-    const int64_t n2 = s.tri * s.cfg.n_chans;
-    int blocks = (int)std::min<int64_t>((n2 + 255) / 256, 16384);
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(xeng::dump_kernel, dim3(blocks), dim3(256), 0, st,
-                       (const uint32_t *)s.d_acc, out, n2, s.tri);
-    HIP_TRY(hipGetLastError());
+    const unsigned gx = (unsigned)((s.tri + xeng::DUMP_PER_WG - 1) / xeng::DUMP_PER_WG);
+    for (int c0 = 0; c0 < s.cfg.n_chans; c0 += 65535) {
+        const int nc = std::min(65535, s.cfg.n_chans - c0);
+        hipLaunchKernelGGL(xeng::dump_kernel, dim3(gx, (unsigned)nc), dim3(256), 0, st,
+                           (const uint2 *)s.d_acc, (uint2 *)out, (int32_t)s.tri, c0);
+        HIP_TRY(hipGetLastError());
+    }
     return XENG_OK;
 }
 
