@@ -72,7 +72,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(samples, n_inputs, n_chans, n_time, budget_s=15.0):
+def cpu_baseline(samples, n_inputs, n_chans, n_time, in_bits=4, budget_s=15.0):
     """Time the CPU oracle on a bounded sample of the same gulp (whole channels)."""
     import numpy as np
 
@@ -82,14 +82,14 @@ def cpu_baseline(samples, n_inputs, n_chans, n_time, budget_s=15.0):
     cores = oracle.num_threads()
     # calibrate on one channel, then size the sample to about budget_s seconds
     t0 = time.perf_counter()
-    oracle.correlate(samples, 4, chans=[0])
+    oracle.correlate(samples, in_bits, chans=[0])
     one = time.perf_counter() - t0
     n_sel = int(max(1, min(n_chans, round(budget_s / max(one, 1e-3) * cores / 2))))
     n_sel = max(cores, (n_sel // cores) * cores) if n_sel >= cores else n_sel
     n_sel = min(n_sel, n_chans)
     chans = np.linspace(0, n_chans - 1, n_sel).round().astype(int).tolist()
     t0 = time.perf_counter()
-    oracle.correlate(samples, 4, chans=chans)
+    oracle.correlate(samples, in_bits, chans=chans)
     dt = time.perf_counter() - t0
     cmac = n_sel * tri * n_time
     return {"value": cmac * OPS_PER_CMAC / dt / 1e12, "unit": "Tops/s", "cores": cores,
@@ -105,6 +105,12 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--workload", default="leda_gulp",
+                    choices=["leda_gulp", "fp8_variant", "int8_variant"],
+                    help="input shape (the default is the headline configuration; the others "
+                         "time the precision variants)")
+    ap.add_argument("--engine", default=None, choices=["i8", "fp8"],
+                    help="arithmetic engine (default: fp8 for fp8_variant, else i8)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (3 times), the "
                          "reference for scaling HBM byte counters, and exit")
@@ -130,17 +136,20 @@ def main():
     from paper_1411_3751_amd import Correlator
 
     torch.cuda.set_device(0)
-    name = "leda_gulp"
+    name = args.workload
+    engine = args.engine or ("fp8" if name == "fp8_variant" else "i8")
     log("generating workload %s ..." % name)
     samples, _, _, meta = synth.workload(name)
     N, F, T = meta["n_inputs"], meta["n_chans"], meta["n_time"]
+    in_bits = meta["in_bits"]
     tri = N * (N + 1) // 2
     cmac_per_step = F * tri * T
     d_samples = torch.from_numpy(samples).cuda()
     out = torch.empty((F, tri, 2), dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
 
-    corr = Correlator([dict(n_inputs=N, n_chans=F, n_time=T, in_bits=4)], stream=stream)
+    corr = Correlator([dict(n_inputs=N, n_chans=F, n_time=T, in_bits=in_bits,
+                            engine=1 if engine == "fp8" else 0)], stream=stream)
     log("plan:", json.dumps(corr.plan()))
 
     def step():
@@ -188,21 +197,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8",
+        "dtype": "fp8_e4m3" if engine == "fp8" else "int8",
         "data": "synthetic",
-        "config": {"workload": "leda_gulp", "n_inputs": N, "n_chans": F, "n_time": T,
-                   "in_bits": 4, "engine": "i8"},
+        "config": {"workload": name, "n_inputs": N, "n_chans": F, "n_time": T,
+                   "in_bits": in_bits, "engine": engine},
         "cmac_per_s": cmac_per_step / (ms_step * 1e-3),
         "pct_int8_peak": round(100.0 * value / peak, 2),
         "rtf_gulp": round(stream_s / (ms_step * 1e-3), 1),
         "ms_kernel": round(ms_kernel, 4),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "traffic": hbm_traffic(KERNEL, "leda_gulp")},
+                     "traffic": hbm_traffic(KERNEL, name) if engine == "i8" and in_bits == 4
+                     else None},
     }
     if not args.no_cpu:
         log("timing the CPU oracle on a sample ...")
-        res["cpu_baseline"] = cpu_baseline(samples, N, F, T)
+        res["cpu_baseline"] = cpu_baseline(samples, N, F, T, in_bits)
     print(json.dumps(res), flush=True)
 
 

@@ -32,9 +32,11 @@
  * Exactness: every result is the exact integer sum. The library refuses
  * (XENG_ERANGE, before launching anything) a call that would let any sum
  * leave int32: at most XENG_MAX_DUMP_SAMPLES_4BIT samples per dump for 4-bit
- * input, XENG_MAX_DUMP_SAMPLES_8BIT for 8-bit input. The FP8 engine keeps
- * every float partial sum below 2^24, so it additionally limits one call to
- * XENG_MAX_CALL_SAMPLES_FP8 samples.
+ * input, XENG_MAX_DUMP_SAMPLES_8BIT for 8-bit input. The FP8 engine sums at
+ * most XENG_MAX_CALL_SAMPLES_FP8 samples in fp32 at a time (every partial sum
+ * stays below 2^24, where fp32 is exact) and adds each such segment into the
+ * int32 accumulator, so its calls may be of any length and its dump bound is
+ * the 4-bit one.
  *
  * Streams and ownership: xeng_correlate and xeng_dump enqueue work on the
  * context's HIP stream and return; the caller keeps the sample buffers valid
@@ -61,11 +63,11 @@ extern "C" {
 #define XENG_EHIP 4   /* a HIP runtime call failed; see xeng_last_error() */
 
 #define XENG_ENGINE_I8 0  /* int8 MFMA, int32 accumulation */
-#define XENG_ENGINE_FP8 1 /* FP8 (OCP e4m3) MFMA, fp32 accumulation; in_bits == 4 only */
+#define XENG_ENGINE_FP8 1 /* FP8 (OCP e4m3) MFMA, fp32 partial sums; in_bits == 4 and N % 16 == 0 */
 
 #define XENG_MAX_DUMP_SAMPLES_4BIT 16777215LL /* floor((2^31 - 1) / 128) */
 #define XENG_MAX_DUMP_SAMPLES_8BIT 65535LL    /* floor((2^31 - 1) / 32768) */
-#define XENG_MAX_CALL_SAMPLES_FP8 32768LL     /* keeps fp32 partial sums < 2^24 */
+#define XENG_MAX_CALL_SAMPLES_FP8 32768LL     /* samples per fp32 partial sum: 128 * 2^15 < 2^24 */
 
 typedef struct xeng_ctx xeng_ctx; /* opaque, library-owned */
 

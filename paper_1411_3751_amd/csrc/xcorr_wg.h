@@ -139,13 +139,121 @@ __device__ __forceinline__ void wg_mfma(const WgOps &o, i32x16 (&accR)[2][2], i3
         }
 }
 
+// ---- FP8 engine (OCP e4m3 operands, fp32 accumulation) -----------------
+//
+// Every 4-bit value v in [-8, 7] and every product of two of them is exact
+// in e4m3 / fp32. A nibble becomes its e4m3 code by a 16-entry table lookup
+// done as two v_perm_b32 byte lookups (v >= 0 and v < 0 halves, indexed by
+// the nibble's low 3 bits) merged under a per-byte sign mask. The mask comes
+// from v_perm_b32's sign-replicating selectors 8..11, which copy bit 7 of
+// bytes 1, 3, 5, 7 of the 8-byte source {S0 : S1}: with S1 = w << 8 and
+// S0 = w those are bytes 0, 2, 1, 3 of w.
+//
+// The operands need no ~im trick here (e4m3 holds +8), so the float
+// accumulators hold Re V and Im V themselves; a segment of at most SEG_T
+// samples keeps every partial sum at most 128 * 2^15 = 2^22 < 2^24, where
+// fp32 is exact, and the flush converts them to int32 exactly.
+constexpr int ENG_I8 = 0;
+constexpr int ENG_F8 = 1;
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef int32_t i32x8 __attribute__((ext_vector_type(8)));
+
+// e4m3 codes of k and of k - 8 for k = 0..7 (bytes 0..3 in the S1 word,
+// 4..7 in the S0 word)
+constexpr uint32_t F8_POS_LO = 0x44403800u; // 0, 1, 2, 3
+constexpr uint32_t F8_POS_HI = 0x4E4C4A48u; // 4, 5, 6, 7
+constexpr uint32_t F8_NEG_LO = 0xCACCCED0u; // -8, -7, -6, -5
+constexpr uint32_t F8_NEG_HI = 0xB8C0C4C8u; // -4, -3, -2, -1
+constexpr uint32_t F8_SIGNSEL = 0x0B090A08u; // bit 7 of bytes 0, 1, 2, 3 of w
+
+// idx: low 3 bits of 4 nibbles (one per byte); neg: 0xFF in the bytes whose
+// nibble is negative
+__device__ __forceinline__ uint32_t f8_lookup(uint32_t idx, uint32_t neg)
+{
+    const uint32_t p = __builtin_amdgcn_perm(F8_POS_HI, F8_POS_LO, idx);
+    const uint32_t n = __builtin_amdgcn_perm(F8_NEG_HI, F8_NEG_LO, idx);
+    return (n & neg) | (p & ~neg);
+}
+
+// e4m3 codes of the real parts (high nibbles) of 4 packed samples
+__device__ __forceinline__ uint32_t f8_re(uint32_t w)
+{
+    return f8_lookup((w >> 4) & 0x07070707u, __builtin_amdgcn_perm(w, w << 8, F8_SIGNSEL));
+}
+
+// e4m3 codes of the imaginary parts (low nibbles) of 4 packed samples
+__device__ __forceinline__ uint32_t f8_im(uint32_t w)
+{
+    const uint32_t w4 = w << 4;
+    return f8_lookup(w & 0x07070707u, __builtin_amdgcn_perm(w4, w4 << 8, F8_SIGNSEL));
+}
+
+// raw dword d (0..7) of side sd, block blk of a stage: K steps 0 and 1 of
+// the int8 layout concatenated (A and B lanes hold the same samples at the
+// same positions, so any fixed order of K within the lane is valid)
+__device__ __forceinline__ uint32_t wg_raw_dw(const WgRaw &R, int sd, int blk, int d)
+{
+    const i32x2 v = R[d >> 2][sd][blk][(d >> 1) & 1];
+    return (uint32_t)((d & 1) ? v.y : v.x);
+}
+
+// One stage (64 samples) of the FP8 engine: 16 v_mfma_scale_f32_32x32x64_f8f6f4
+// (scales 2^0) over 2 x 2 tiles of 32 x 32:
+//   accR += re_I re_J + im_I im_J,  accI += im_I re_J + re_I (-im_J).
+__device__ __forceinline__ void wg_f8_stage(const WgRaw &R, f32x16 (&accR)[2][2],
+                                            f32x16 (&accI)[2][2])
+{
+    i32x8 reI[2], imI[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const uint32_t w = wg_raw_dw(R, 0, x, d);
+            reI[x][d] = (int32_t)f8_re(w);
+            imI[x][d] = (int32_t)f8_im(w);
+        }
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+        // the negated imaginary operand replaces the plain one in the same
+        // registers once the plain one's products are issued
+        i32x8 reJ, imJ;
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const uint32_t w = wg_raw_dw(R, 1, y, d);
+            reJ[d] = (int32_t)f8_re(w);
+            imJ[d] = (int32_t)f8_im(w);
+        }
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            accR[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(reI[x], reJ, accR[x][y],
+                                                                         0, 0, 0, 127, 0, 127);
+            accI[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(imI[x], reJ, accI[x][y],
+                                                                         0, 0, 0, 127, 0, 127);
+            accR[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(imI[x], imJ, accR[x][y],
+                                                                         0, 0, 0, 127, 0, 127);
+        }
+        const i32x8 niJ = imJ ^ (int32_t)0x80808080u;
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+            accI[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(reI[x], niJ, accI[x][y],
+                                                                         0, 0, 0, 127, 0, 127);
+    }
+}
+
+// accumulator element -> int32 word of the raw accumulator
+__device__ __forceinline__ uint32_t acc_word(int32_t v) { return (uint32_t)(v >> 8); }
+__device__ __forceinline__ uint32_t acc_word(float v) { return (uint32_t)(int32_t)v; }
+
 // OCC workgroups per CU: OCC = 1 keeps an 8-deep ring and software-pipelines
 // the next stage's fragment reads and unpack under this stage's MFMAs;
 // OCC = 2 halves the ring and the registers so that two workgroups share a
 // CU and each one's barrier and LDS latency is covered by the other's MFMAs.
-template <int OCC>
+template <int OCC, int ENG>
 __global__ __launch_bounds__(WG_THREADS, OCC) void xcorr4_wg_kernel(WgArgs a)
 {
+    static_assert(ENG == ENG_I8 || OCC == 2, "the FP8 engine runs at occupancy 2");
+    typedef typename std::conditional<ENG == ENG_F8, f32x16, i32x16>::type AccT;
     constexpr int WG_NBUF = OCC == 1 ? 8 : 4;   // LDS ring depth (stages)
     __shared__ __attribute__((aligned(16))) uint8_t lds[WG_NBUF * WG_STAGE];
 
@@ -256,8 +364,12 @@ __global__ __launch_bounds__(WG_THREADS, OCC) void xcorr4_wg_kernel(WgArgs a)
 
     // ---- read cursor: the stage whose fragments are read next, and the
     // transpose-load offsets of its tile's role
+    // Row tau = 32 k + 8 i + (16 (G >> 1) + m) of load (k, i) differs from
+    // the lane's base row by a multiple of 8, so its slot swizzle (tau & 7 =
+    // m) is the base row's: one register per (side, block), and the
+    // 8192 k + 2048 i parts are immediate offsets.
     const int G = lane >> 4, m = (lane >> 1) & 7, h = lane & 1;
-    int fo[2][2][2][2]; // (K step, side, block, load) -> byte offset in a stage
+    int fo[2][2]; // (side, block) -> byte offset of load (0, 0) in a stage
     int r_item = it_begin, r_stage = 0, r_nstage = 0, r_tcount = 0;
     auto r_setup = [&](int it) {
         const WgItem w = item_at(it);
@@ -268,17 +380,13 @@ __global__ __launch_bounds__(WG_THREADS, OCC) void xcorr4_wg_kernel(WgArgs a)
         bool write;
         role(w, ic, jc, r0, c0, write);
 #pragma unroll
-        for (int k = 0; k < 2; ++k)
+        for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
-            for (int sd = 0; sd < 2; ++sd)
-#pragma unroll
-                for (int blk = 0; blk < 2; ++blk)
-#pragma unroll
-                    for (int i = 0; i < 2; ++i) {
-                        const int tau = 32 * k + 16 * (G >> 1) + 8 * i + m;
-                        const int c = (sd == 0 ? ic : jc) + 2 * blk + (G & 1);
-                        fo[k][sd][blk][i] = tau * WG_ROWB + 16 * wg_slot(tau, c) + 8 * h;
-                    }
+            for (int blk = 0; blk < 2; ++blk) {
+                const int tau = 16 * (G >> 1) + m;
+                const int c = (sd == 0 ? ic : jc) + 2 * blk + (G & 1);
+                fo[sd][blk] = tau * WG_ROWB + 16 * wg_slot(tau, c) + 8 * h;
+            }
     };
 
     // Make the read cursor's stage s visible to every wave: this wave's
@@ -315,17 +423,17 @@ __global__ __launch_bounds__(WG_THREADS, OCC) void xcorr4_wg_kernel(WgArgs a)
 #pragma unroll
                     for (int i = 0; i < 2; ++i)
                         R[k][sd][blk][i] = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
-                            (lds_i32x2 *)(b + fo[k][sd][blk][i]));
+                            (lds_i32x2 *)(b + fo[sd][blk] + (32 * k + 8 * i) * WG_ROWB));
     };
 
-    i32x16 accR[2][2], accI[2][2];
+    AccT accR[2][2], accI[2][2];
     WgRaw RA, RB;
     WgOps O0, O1;
     r_setup(it_begin);
     prep_stage(0);
     read_frags(0, RA);
     r_advance();
-    wg_unpack(RA, 0, O0);
+    if constexpr (ENG == ENG_I8) wg_unpack(RA, 0, O0);
     int s = 0; // global index of the stage being multiplied
 
     for (int it = it_begin; it < it_end; ++it) {
@@ -340,10 +448,10 @@ __global__ __launch_bounds__(WG_THREADS, OCC) void xcorr4_wg_kernel(WgArgs a)
         for (int x = 0; x < 2; ++x)
 #pragma unroll
             for (int y = 0; y < 2; ++y) {
-                accR[x][y] = i32x16{};
-                accI[x][y] = i32x16{};
+                accR[x][y] = AccT{};
+                accI[x][y] = AccT{};
             }
-        if (OCC == 1) {
+        if constexpr (OCC == 1) {
             for (int k = 0; k < nst; ++k, ++s) {
                 if (issued < n_total) d_issue();
                 if (s + 1 < n_total) prep_stage(s + 1);
@@ -374,10 +482,14 @@ __global__ __launch_bounds__(WG_THREADS, OCC) void xcorr4_wg_kernel(WgArgs a)
             // and multiply one K step at a time, then publish and read the next
             for (int k = 0; k < nst; ++k, ++s) {
                 if (issued < n_total) d_issue();
-                wg_unpack(RA, 0, O0);
-                wg_mfma(O0, accR, accI);
-                wg_unpack(RA, 1, O0);
-                wg_mfma(O0, accR, accI);
+                if constexpr (ENG == ENG_I8) {
+                    wg_unpack(RA, 0, O0);
+                    wg_mfma(O0, accR, accI);
+                    wg_unpack(RA, 1, O0);
+                    wg_mfma(O0, accR, accI);
+                } else {
+                    wg_f8_stage(RA, accR, accI);
+                }
                 if (s + 1 < n_total) {
                     prep_stage(s + 1);
                     read_frags((s + 1) % WG_NBUF, RA);
@@ -426,8 +538,8 @@ __global__ __launch_bounds__(WG_THREADS, OCC) void xcorr4_wg_kernel(WgArgs a)
                     for (int e = 0; e < 4; ++e)
 #pragma unroll
                         for (int y = 0; y < 2; ++y) {
-                            const u32x2 v = {old[e][y].x + (uint32_t)(accR[x][y][4 * q + e] >> 8),
-                                             old[e][y].y + (uint32_t)(accI[x][y][4 * q + e] >> 8)};
+                            const u32x2 v = {old[e][y].x + acc_word(accR[x][y][4 * q + e]),
+                                             old[e][y].y + acc_word(accI[x][y][4 * q + e])};
                             __builtin_amdgcn_raw_buffer_store_b64(v, vrs, (int)off[e][y], 0, 0);
                         }
                 } else {
@@ -435,8 +547,8 @@ __global__ __launch_bounds__(WG_THREADS, OCC) void xcorr4_wg_kernel(WgArgs a)
                     for (int e = 0; e < 4; ++e)
 #pragma unroll
                         for (int y = 0; y < 2; ++y) {
-                            const u32x2 v = {(uint32_t)(accR[x][y][4 * q + e] >> 8),
-                                             (uint32_t)(accI[x][y][4 * q + e] >> 8)};
+                            const u32x2 v = {acc_word(accR[x][y][4 * q + e]),
+                                             acc_word(accI[x][y][4 * q + e])};
                             __builtin_amdgcn_raw_buffer_store_b64(v, vrs, (int)off[e][y], 0, 0);
                         }
                 }

@@ -70,6 +70,7 @@ struct Sub {
 
 // One persistent-kernel launch group: the subarrays it covers and its schedule.
 struct WavePlan {
+    int engine = XENG_ENGINE_I8;     // every subarray of a plan uses this engine
     std::vector<int> subs;           // context subarray indices, in launch order
     std::vector<xeng::WgItem> items; // flat, grouped per workgroup
     std::vector<int32_t> wg_begin;   // [n_wg + 1]
@@ -132,8 +133,11 @@ int validate(const xeng_subarray &s, int idx)
         return fail(XENG_EINVAL, "subarray %d: in_bits %d is not 4 or 8", idx, s.in_bits);
     if (s.engine != XENG_ENGINE_I8 && s.engine != XENG_ENGINE_FP8)
         return fail(XENG_EINVAL, "subarray %d: unknown engine %d", idx, s.engine);
-    if (s.engine == XENG_ENGINE_FP8)
-        return fail(XENG_EINVAL, "subarray %d: the FP8 engine is not available in this build", idx);
+    if (s.engine == XENG_ENGINE_FP8 && s.in_bits != 4)
+        return fail(XENG_EINVAL, "subarray %d: the FP8 engine takes 4-bit input only", idx);
+    if (s.engine == XENG_ENGINE_FP8 && s.n_inputs % 16 != 0)
+        return fail(XENG_EINVAL, "subarray %d: the FP8 engine needs n_inputs a multiple of 16 (got %d)",
+                    idx, s.n_inputs);
     const int64_t tri = (int64_t)s.n_inputs * (s.n_inputs + 1) / 2;
     if (tri * (int64_t)s.n_chans * 2 > ((int64_t)1 << 40))
         return fail(XENG_EINVAL, "subarray %d: output too large", idx);
@@ -294,8 +298,12 @@ int launch_wave(xeng_ctx *ctx, WavePlan &p, const void *const *d_samples)
         }
         a.items = p.d_items;
         a.wg_begin = p.d_wg_begin;
-        hipLaunchKernelGGL(xeng::xcorr4_wg_kernel<WG_OCC>, dim3(p.n_wg), dim3(xeng::WG_THREADS), 0,
-                           ctx->stream, a);
+        if (p.engine == XENG_ENGINE_FP8)
+            hipLaunchKernelGGL((xeng::xcorr4_wg_kernel<2, xeng::ENG_F8>), dim3(p.n_wg),
+                               dim3(xeng::WG_THREADS), 0, ctx->stream, a);
+        else
+            hipLaunchKernelGGL((xeng::xcorr4_wg_kernel<WG_OCC, xeng::ENG_I8>), dim3(p.n_wg),
+                               dim3(xeng::WG_THREADS), 0, ctx->stream, a);
         HIP_TRY(hipGetLastError());
         for (int k : p.subs) ctx->subs[k].acc_zero = false;
     }
@@ -387,18 +395,25 @@ int xeng_create(const xeng_subarray *subs, int n_subs, void *hip_stream, xeng_ct
         }
         if (s.wave) wave_subs.push_back(k);
     }
-    // one launch group for all wave-path subarrays when each fits one
-    // segment; otherwise one group per subarray
-    bool one_group = true;
-    for (int k : wave_subs)
-        if (ctx->subs[k].cfg.n_time > xeng::SEG_T) one_group = false;
-    if (!wave_subs.empty()) {
+    // per engine: one launch group for all its wave-path subarrays when each
+    // fits one segment; otherwise one group per subarray
+    for (int eng : {XENG_ENGINE_I8, XENG_ENGINE_FP8}) {
+        std::vector<int> es;
+        bool one_group = true;
+        for (int k : wave_subs)
+            if (ctx->subs[k].cfg.engine == eng) {
+                es.push_back(k);
+                if (ctx->subs[k].cfg.n_time > xeng::SEG_T) one_group = false;
+            }
+        if (es.empty()) continue;
         if (one_group) {
             ctx->plans.emplace_back();
-            ctx->plans.back().subs = wave_subs;
+            ctx->plans.back().engine = eng;
+            ctx->plans.back().subs = es;
         } else {
-            for (int k : wave_subs) {
+            for (int k : es) {
                 ctx->plans.emplace_back();
+                ctx->plans.back().engine = eng;
                 ctx->plans.back().subs = {k};
             }
         }

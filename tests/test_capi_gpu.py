@@ -19,7 +19,8 @@ def test_invalid_arguments(torch_cuda):
     for bad in [dict(n_inputs=0, n_chans=1, n_time=1), dict(n_inputs=4, n_chans=0, n_time=1),
                 dict(n_inputs=4, n_chans=1, n_time=0), dict(n_inputs=4, n_chans=1, n_time=8, in_bits=6),
                 dict(n_inputs=4, n_chans=1, n_time=8, engine=7),
-                dict(n_inputs=4, n_chans=1, n_time=8, in_bits=8, engine=1)]:
+                dict(n_inputs=4, n_chans=1, n_time=8, in_bits=8, engine=1),
+                dict(n_inputs=40, n_chans=1, n_time=8, in_bits=4, engine=1)]:
         with pytest.raises(XengError) as ei:
             Correlator([bad])
         assert ei.value.code == XENG_EINVAL
