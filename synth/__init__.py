@@ -7,11 +7,17 @@ inputs from it without sharing any of the method.
 """
 from .gen import (  # noqa: F401
     SEED_BASE,
-    draw_stream,
+    TONE_AMP,
+    TONE_NU,
+    WORKLOADS,
+    build,
+    drift_phase,
+    fixed_tone,
     pack4,
     pack8,
+    stream,
+    thresholds,
     tone_channels,
     tone_series,
     workload,
-    WORKLOADS,
 )

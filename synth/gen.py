@@ -5,27 +5,64 @@ samples after one band-average digital gain (Section 2.2); its test plan adds
 continuous-wave tones (Section 5). The sky data itself is not available, so
 these generators stand in for it:
 
-* every real and imaginary component is ``clip(rint(sigma * g + a), lo, hi)``
-  with ``g ~ N(0, 1)`` (numpy ``rint``: round half to even) and ``a`` the tone
-  component where a tone is present, else 0;
+* every real and imaginary component has the law of
+  ``clip(round(sigma * g + a), lo, hi)`` with ``g ~ N(0, 1)`` and ``a`` the
+  tone component where a tone is present, else 0;
 * 4-bit streams use ``[lo, hi] = [-8, 7]``; 8-bit streams ``[-127, 127]``;
-* the common tone is ``s(t) = A exp(i 2 pi (nu t + phi0))``, identical on all
-  inputs, in the channels ``(2m+1) F / 8`` for ``m = 0..3``.
+* the common tone is ``s(t) = A exp(i phi(t))``, identical on all inputs, in
+  the channels ``(2m+1) F / 8`` for ``m = 0..3``; ``phi(t) = 2 pi (nu t +
+  phi0)`` for a fixed tone, or a phase-continuous drift across gulps.
+
+Each component is drawn from a counter (stream seed, absolute time, channel,
+input, re/im) through the SplitMix64 output function and a table of uint32
+thresholds (``csynth.c`` states the definition; ``gpu_gen.hip`` implements the
+same one on the GPU), so any time range or channel subset of a stream can be
+regenerated on its own, bit for bit, on the host or on the device.
 
 Layout of a stream is ``[time][channel][input]`` (post corner turn, Fig. 2).
-Draws are made per block of ``BLOCK_T`` time samples with a generator seeded
-by ``(seed, block index)``, so the result does not depend on how many blocks
-are drawn at once or in which thread.
 """
 from __future__ import annotations
 
+import ctypes
 import os
-from concurrent.futures import ThreadPoolExecutor
+import subprocess
 
 import numpy as np
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsynth.so")
+SRC = os.path.join(HERE, "csynth.c")
+
 SEED_BASE = 14113751
-BLOCK_T = 64
+TONE_AMP = 1.5
+TONE_NU = 1.0 / 128.0
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the host generator (gcc, OpenMP) next to its source."""
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
+        tmp = LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+                               SRC, "-o", tmp])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(LIB_PATH)
+        lib.synth_fill.restype = None
+        lib.synth_fill.argtypes = [
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
+            ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+            ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+            ctypes.c_void_p, ctypes.c_int]
+        _lib = lib
+    return _lib
 
 
 def tone_channels(n_chans: int) -> list[int]:
@@ -36,60 +73,71 @@ def tone_channels(n_chans: int) -> list[int]:
 
 
 def tone_series(t0: int, n_t: int, amp: float, nu: float, phi0: float = 0.0):
-    """Complex tone amplitude a(t) = amp * exp(i 2 pi (nu t + phi0)) for t in [t0, t0+n_t)."""
+    """Tone components amp * (cos, sin)(2 pi (nu t + phi0)) for t in [t0, t0+n_t)."""
     t = np.arange(t0, t0 + n_t, dtype=np.float64)
     ph = 2.0 * np.pi * (nu * t + phi0)
     return amp * np.cos(ph), amp * np.sin(ph)
 
 
-def _draw_block(seed: int, blk: int, n_t: int, n_chans: int, n_inputs: int,
-                sigma: float, lo: int, hi: int, tone):
-    rng = np.random.default_rng([seed, blk])
-    shape = (n_t, n_chans, n_inputs)
-    re = rng.standard_normal(shape, dtype=np.float32)
-    im = rng.standard_normal(shape, dtype=np.float32)
-    re *= np.float32(sigma)
-    im *= np.float32(sigma)
-    if tone is not None:
-        amp, nu, phi0, chans = tone
-        if chans:
-            tr, ti = tone_series(blk * BLOCK_T, n_t, amp, nu, phi0)
-            cs = np.asarray(chans)
-            re[:, cs, :] += tr.astype(np.float32)[:, None, None]
-            im[:, cs, :] += ti.astype(np.float32)[:, None, None]
-    np.rint(re, out=re)
-    np.rint(im, out=im)
-    np.clip(re, lo, hi, out=re)
-    np.clip(im, lo, hi, out=im)
-    return re.astype(np.int8), im.astype(np.int8)
+def drift_phase(t: np.ndarray, gulp: int, nu0: float = TONE_NU, dnu: float = 1e-5):
+    """Phase (radians) of a tone whose frequency steps by dnu per gulp of
+    ``gulp`` samples (nu_g = nu0 + g dnu), continuous across gulps."""
+    t = np.asarray(t, np.int64)
+    g = t // gulp
+    # phase at the start of gulp g: 2 pi gulp sum_{h<g} nu_h
+    start = 2.0 * np.pi * gulp * (nu0 * g + dnu * g * (g - 1) / 2.0)
+    return start + 2.0 * np.pi * (nu0 + dnu * g) * (t - g * gulp)
 
 
-def draw_stream(seed: int, n_time: int, n_chans: int, n_inputs: int, sigma: float,
-                lo: int = -8, hi: int = 7, tone=None, threads: int | None = None):
-    """Integer components (re, im), each int8 ``[n_time][n_chans][n_inputs]``.
+def thresholds(lo: int, hi: int, sigma: float, a=0.0) -> np.ndarray:
+    """uint32 thresholds floor(2^32 Phi((lo + k + 1/2 - a) / sigma)), k < hi - lo.
 
-    ``tone`` is ``(amp, nu, phi0, channels)`` or ``None``.
+    ``a`` may be an array (one table per entry): the result then has shape
+    ``a.shape + (hi - lo,)``.
     """
-    re = np.empty((n_time, n_chans, n_inputs), np.int8)
-    im = np.empty_like(re)
-    n_blk = (n_time + BLOCK_T - 1) // BLOCK_T
+    from scipy.special import ndtr
+    a = np.asarray(a, np.float64)
+    b = lo + np.arange(hi - lo, dtype=np.float64) + 0.5
+    z = (b - a[..., None]) / sigma
+    th = np.floor(ndtr(z) * 4294967296.0)
+    return np.clip(th, 0, 4294967295).astype(np.uint32)
 
-    def work(b):
-        t0 = b * BLOCK_T
-        n_t = min(BLOCK_T, n_time - t0)
-        r, i = _draw_block(seed, b, n_t, n_chans, n_inputs, sigma, lo, hi, tone)
-        re[t0:t0 + n_t] = r
-        im[t0:t0 + n_t] = i
 
-    if threads is None:
-        threads = min(16, os.cpu_count() or 1)
-    if n_blk == 1 or threads == 1:
-        for b in range(n_blk):
-            work(b)
+def stream(seed: int, n_time: int, n_chans: int, n_inputs: int, in_bits: int, sigma: float,
+           t0: int = 0, chans=None, tone=None, components: bool = False, threads: int = 0):
+    """Draw times [t0, t0 + n_time) of a stream for channels ``chans`` (all if None).
+
+    ``tone`` is ``(amp, phase_fn, tone_chans)`` with ``phase_fn(t)`` the phase
+    in radians at absolute times t, or None. Returns ``(samples, re, im)``:
+    samples uint8 ``[T][S][N]`` (4-bit) or int8 ``[T][S][N][2]`` (8-bit); re, im
+    int8 ``[T][S][N]`` when ``components`` else None.
+    """
+    lo, hi = (-8, 7) if in_bits == 4 else (-127, 127)
+    n_lv = hi - lo + 1
+    sel = np.arange(n_chans, dtype=np.int32) if chans is None else np.asarray(chans, np.int32)
+    n_sel = int(sel.size)
+    if in_bits == 4:
+        out = np.empty((n_time, n_sel, n_inputs), np.uint8)
     else:
-        with ThreadPoolExecutor(threads) as ex:
-            list(ex.map(work, range(n_blk)))
-    return re, im
+        out = np.empty((n_time, n_sel, n_inputs, 2), np.int8)
+    re = np.empty((n_time, n_sel, n_inputs), np.int8) if components else None
+    im = np.empty((n_time, n_sel, n_inputs), np.int8) if components else None
+    base = thresholds(lo, hi, sigma)
+    thr_tone = None
+    tone_mask = None
+    if tone is not None and tone[2]:
+        amp, phase_fn, tchans = tone
+        ph = phase_fn(np.arange(t0, t0 + n_time, dtype=np.int64))
+        a = np.stack([amp * np.cos(ph), amp * np.sin(ph)], axis=1)  # [T][2]
+        thr_tone = np.ascontiguousarray(thresholds(lo, hi, sigma, a))  # [T][2][L-1]
+        tone_mask = np.zeros(n_chans, np.uint8)
+        tone_mask[list(tchans)] = 1
+    lib = _load()
+    ptr = lambda x: None if x is None else x.ctypes.data
+    lib.synth_fill(ptr(out), ptr(re), ptr(im), in_bits, n_time, t0, n_chans, n_inputs,
+                   ptr(sel), n_sel, ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), lo, n_lv,
+                   ptr(base), ptr(thr_tone), ptr(tone_mask), int(threads))
+    return out, re, im
 
 
 def pack4(re: np.ndarray, im: np.ndarray) -> np.ndarray:
@@ -116,29 +164,31 @@ WORKLOADS = {
     "fp8_variant": dict(n_inputs=512, n_chans=256, n_time=16384, sigma=2.5, in_bits=4, tone=False, k=2),
     "int8_variant": dict(n_inputs=512, n_chans=256, n_time=16384, sigma=20.0, in_bits=8, tone=False, k=2),
 }
-TONE_AMP = 1.5
-TONE_NU = 1.0 / 128.0
+
+
+def fixed_tone(n_chans: int, amp: float = TONE_AMP, nu: float = TONE_NU, phi0: float = 0.0):
+    """The workloads' tone: amp exp(i 2 pi (nu t + phi0)) in tone_channels(F)."""
+    return (amp, lambda t: 2.0 * np.pi * (nu * np.asarray(t, np.float64) + phi0),
+            tone_channels(n_chans))
 
 
 def workload(name: str, subarray: int = 0, n_time: int | None = None,
-             n_chans: int | None = None, n_inputs: int | None = None):
+             n_chans: int | None = None, n_inputs: int | None = None, chans=None,
+             components: bool = False):
     """Draw a named workload; returns ``(samples, re, im, meta)``.
 
     ``samples`` is the packed device format (uint8 ``[T][F][N]`` for 4-bit,
-    int8 ``[T][F][N][2]`` for 8-bit). Sizes can be overridden to draw a smaller
-    instance with the same recipe.
+    int8 ``[T][F][N][2]`` for 8-bit), restricted to ``chans`` if given. Sizes
+    can be overridden to draw a smaller instance with the same recipe. ``re``
+    and ``im`` are the int8 components when ``components`` is true, else None.
     """
     w = dict(WORKLOADS[name])
     T = n_time or w["n_time"]
     F = n_chans or w["n_chans"]
     N = n_inputs or w["n_inputs"]
     seed = SEED_BASE + w["k"] + 100 * subarray
-    if w["in_bits"] == 4:
-        lo, hi = -8, 7
-    else:
-        lo, hi = -127, 127
-    tone = (TONE_AMP, TONE_NU, 0.0, tone_channels(F)) if w["tone"] else None
-    re, im = draw_stream(seed, T, F, N, w["sigma"], lo, hi, tone)
-    samples = pack4(re, im) if w["in_bits"] == 4 else pack8(re, im)
+    tone = fixed_tone(F) if w["tone"] else None
+    samples, re, im = stream(seed, T, F, N, w["in_bits"], w["sigma"], chans=chans, tone=tone,
+                             components=components)
     meta = dict(w, n_time=T, n_chans=F, n_inputs=N, seed=seed)
     return samples, re, im, meta

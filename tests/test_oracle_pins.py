@@ -218,7 +218,8 @@ def test_tone_lands_in_its_channels(oracle_lib):
     # statistical sanity of the generator + definition, not parity: the common
     # tone (amplitude 1.5) shows as Re V_ij / T ~ |A|^2 = 2.25 for i != j only in
     # the tone channels
-    s, re, im, meta = synth.workload("leda_gulp", n_inputs=8, n_chans=16, n_time=4096)
+    s, re, im, meta = synth.workload("leda_gulp", n_inputs=8, n_chans=16, n_time=4096,
+                                     components=True)
     v = oracle_lib.correlate(s, 4)
     cross = [i * (i + 1) // 2 + j for i in range(8) for j in range(i)]
     mean = v[:, cross, 0].mean(axis=1) / meta["n_time"]
@@ -234,7 +235,7 @@ def test_tone_lands_in_its_channels(oracle_lib):
 def test_generator_histogram():
     # the 4-bit draw follows the clipped, rounded Gaussian pmf (sigma 2.5)
     from math import erf, sqrt
-    _, re, im, _ = synth.workload("tiny")
+    _, re, im, _ = synth.workload("tiny", components=True)
     counts = np.bincount(re.ravel().astype(np.int64) + 8, minlength=16)
     n = re.size
     cdf = lambda z: 0.5 * (1 + erf(z / (2.5 * sqrt(2))))
