@@ -27,7 +27,7 @@ PEAK_INT8_OPS = 5.0e15           # MI355X dense int8 MFMA, ops/s
 CHANNEL_HZ = 24.0e3              # channel width of the paper's F-engine (Section 2)
 
 
-KERNEL = "xcorr4_wg_kernel"       # the dominant kernel of a step
+KERNEL = "xcorr_wg_kernel"        # the dominant kernel of a step
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1411_3751_amd", "csrc", f)
                   for f in ("xeng.hip", "xcorr_wg.h", "xcorr_i8.h")]

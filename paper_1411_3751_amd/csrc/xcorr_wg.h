@@ -1,25 +1,26 @@
-// Persistent-workgroup X-engine kernel for 4-bit input (N a multiple of 16).
+// Persistent-workgroup X-engine kernel (4-bit input with N a multiple of 16,
+// 8-bit input with N a multiple of 8).
 //
 // Work is a host-built list of 128 x 128 tiles (subarray, channel, 128-input
 // block I, block J <= I) of the lower block triangle of
-// V[f] = sum_t x(t, f) x(t, f)^H (Section 2.5; Fig. 2 caption). One
-// workgroup of 4 waves runs per CU and walks its own slice of the list.
+// V[f] = sum_t x(t, f) x(t, f)^H (Section 2.5; Fig. 2 caption). Two
+// workgroups of 4 waves run per CU; each walks its own slice of the list.
 //
-// Staging: each stage of TK = 64 time samples of a tile is copied raw
-// ([time][128 I inputs | 128 J inputs], one byte per complex sample) from
-// HBM into an NBUF-deep LDS ring by buffer loads that write LDS directly,
-// issued NBUF - 1 stages ahead. A stage is published to the four waves by
-// one barrier after each wave's own copies have landed.
+// Staging: each stage of a tile is copied raw ([time][128 I inputs | 128 J
+// inputs], as stored in HBM) into a 4-deep LDS ring of 16 KB stages by
+// buffer loads that write LDS directly, issued 3 stages ahead. A stage holds
+// 64 time rows of 4-bit samples (256 bytes per row) or 32 rows of 8-bit
+// samples (512 bytes). It is published to the four waves by one barrier
+// after each wave's own copies have landed.
 //
-// Fragments: ds_read_b64_tr_b8 turns the time-major rows into the K-major
-// operands of v_mfma_i32_32x32x32_i8 (lane l: input l % 32, K group l / 32).
-// Within each group of 16 lanes, lane 2m + h names time row m of half h of
-// a 16-input chunk and lane 8h + j receives input 8h + j at 8 times.
-//
-// Bank layout: chunk c (16 inputs) of time row tau sits in 16-byte slot
-// c ^ (tau & 7) ^ (8 (c & 1)) of the 256-byte row, so the 8 rows a group
-// reads, and the odd/even chunk pairs two neighbouring groups read, hit
-// distinct banks.
+// Fragments: transposing LDS reads turn the time-major rows into the
+// K-major operands of v_mfma_i32_32x32x32_i8 (lane l: input l % 32, K group
+// l / 32). 4-bit rows use ds_read_b64_tr_b8: within each group of 16 lanes,
+// lane 2m + h names time row m of half h of a 16-input chunk and lane 8h + j
+// receives input 8h + j at 8 times. 8-bit rows use ds_read_b64_tr_b16 on
+// (re, im) byte pairs: lane 4m + q names row m, quarter q of a 16-input span
+// and lane k receives input k at 4 times; v_perm splits the pairs into re
+// and im bytes.
 //
 // Each wave computes a 64 x 64 quarter of the tile as 2 x 2 MFMA tiles of
 // 32 x 32. On a diagonal tile (J = I, only the I half is copied) three
@@ -27,10 +28,10 @@
 // one, and wave 3 repeats wave 2's work without writing it (every wave runs
 // the same branch-free stage loop).
 //
-// Per stage a wave waits + barriers for the next stage, reads its raw
-// fragments, and issues its MFMAs while the next K step's operands are
-// unpacked (16*re, 16*im, 16*~im, see xcorr_i8.h). Results go to the raw
-// accumulator (Im holds Im V_ij - S_i; the dump subtracts the diagonal).
+// Operands: re, im and ~im (= -im - 1, so that -(-8) or -(-128) never has to
+// fit in int8); 4-bit values are scaled by 16 by the nibble masks (see
+// xcorr_i8.h). Results go to the raw accumulator (Im holds Im V_ij - S_i with
+// S_i = sum_t re_i; the dump subtracts the diagonal).
 #pragma once
 
 #include <type_traits>
@@ -39,12 +40,47 @@
 
 namespace xeng {
 
-constexpr int WG_ROWB = 256;                   // bytes per staged time row
-constexpr int WG_STAGE = TK * WG_ROWB;         // 16 KB
+constexpr int WG_STAGE = 16384;                      // bytes per LDS stage
+constexpr int WG_NBUF = 4;                           // LDS ring depth (stages)
 constexpr int WG_DMA = WG_STAGE / (WG_THREADS * 16); // 16-byte copies per thread per stage (4)
 constexpr int WG_MAX_SUBS = 16;
 
+// Stage geometry per input width. A staged row is [128 I inputs | 128 J
+// inputs] of one time sample; chunks are 16-byte copy units.
+template <int IN_BITS> struct WgGeom;
+
+template <> struct WgGeom<4> {
+    static constexpr int TKS = 64;   // time rows per stage (two 32-sample K steps)
+    static constexpr int ROWB = 256; // bytes per row
+    static constexpr int NCH = 16;   // chunks per row
+    static constexpr int CIN = 16;   // inputs per chunk
+    static constexpr int BPS = 1;    // bytes per sample
+    // chunk c of row tau sits in slot c ^ (tau & 7) ^ 8 (c & 1): the 8 rows a
+    // tr8 group reads and the odd/even chunk pairs of neighbouring groups hit
+    // distinct banks
+    __device__ static int slot(int tau, int c) { return c ^ (tau & 7) ^ ((c & 1) << 3); }
+    __device__ static int chunk(int tau, int sl)
+    {
+        const int c = sl ^ (tau & 7);
+        return (c & 1) ? (c ^ 8) : c;
+    }
+};
+
+template <> struct WgGeom<8> {
+    static constexpr int TKS = 32;   // time rows per stage (one K step)
+    static constexpr int ROWB = 512;
+    static constexpr int NCH = 32;
+    static constexpr int CIN = 8;
+    static constexpr int BPS = 2;
+    // chunk c of row tau sits in slot c ^ 4 (tau & 3): the 4 rows x 4 chunks
+    // of one half-wave tr16 read cover 16 distinct 16-byte bank groups
+    __device__ static int slot(int tau, int c) { return c ^ ((tau & 3) << 2); }
+    __device__ static int chunk(int tau, int sl) { return sl ^ ((tau & 3) << 2); }
+};
+
 typedef int32_t i32x16 __attribute__((ext_vector_type(16)));
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) i16x4 lds_i16x4;
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 struct WgSub {
@@ -68,15 +104,6 @@ struct WgArgs {
     const WgItem *items;
     const int32_t *wg_begin;     // [n_wg + 1] item ranges per workgroup
 };
-
-__device__ __forceinline__ int wg_slot(int tau, int c) { return c ^ (tau & 7) ^ ((c & 1) << 3); }
-
-// chunk stored in slot `slot` of row tau (inverse of wg_slot)
-__device__ __forceinline__ int wg_chunk(int tau, int slot)
-{
-    int c = slot ^ (tau & 7);
-    return (c & 1) ? (c ^ 8) : c;
-}
 
 // Wait until at most 4 * n of this wave's copies are outstanding, then barrier.
 __device__ __forceinline__ void wg_wait_barrier(int n)
@@ -121,6 +148,34 @@ __device__ __forceinline__ void wg_unpack(const WgRaw &R, int k, WgOps &o)
         o.reJ[y] = (i32x4)(p & 0xF0F0F0F0u);
         o.imJ[y] = (i32x4)im;
         o.niJ[y] = (i32x4)(im ^ 0xF0F0F0F0u);
+    }
+}
+
+// 8-bit stage (one K step): raw load i (0..3) of (side, block) holds 4 times
+// of (re, im) byte pairs; split them into re and im bytes.
+__device__ __forceinline__ i32x2 wg8_raw(const WgRaw &R, int sd, int blk, int i)
+{
+    return R[i >> 1][sd][blk][i & 1];
+}
+
+__device__ __forceinline__ void wg8_split(const WgRaw &R, int sd, int blk, i32x4 &re, i32x4 &im)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const i32x2 v = wg8_raw(R, sd, blk, i);
+        re[i] = (int32_t)__builtin_amdgcn_perm((uint32_t)v.y, (uint32_t)v.x, 0x06040200u);
+        im[i] = (int32_t)__builtin_amdgcn_perm((uint32_t)v.y, (uint32_t)v.x, 0x07050301u);
+    }
+}
+
+__device__ __forceinline__ void wg8_unpack(const WgRaw &R, WgOps &o)
+{
+#pragma unroll
+    for (int x = 0; x < 2; ++x) wg8_split(R, 0, x, o.reI[x], o.imI[x]);
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+        wg8_split(R, 1, y, o.reJ[y], o.imJ[y]);
+        o.niJ[y] = ~o.imJ[y];
     }
 }
 
@@ -241,20 +296,22 @@ __device__ __forceinline__ void wg_f8_stage(const WgRaw &R, f32x16 (&accR)[2][2]
     }
 }
 
-// accumulator element -> int32 word of the raw accumulator
-__device__ __forceinline__ uint32_t acc_word(int32_t v) { return (uint32_t)(v >> 8); }
+// accumulator element -> int32 word of the raw accumulator (4-bit int8
+// products carry a factor 256)
+template <int IN_BITS>
+__device__ __forceinline__ uint32_t acc_word(int32_t v) { return (uint32_t)(IN_BITS == 4 ? v >> 8 : v); }
+template <int IN_BITS>
 __device__ __forceinline__ uint32_t acc_word(float v) { return (uint32_t)(int32_t)v; }
 
-// OCC workgroups per CU: OCC = 1 keeps an 8-deep ring and software-pipelines
-// the next stage's fragment reads and unpack under this stage's MFMAs;
-// OCC = 2 halves the ring and the registers so that two workgroups share a
-// CU and each one's barrier and LDS latency is covered by the other's MFMAs.
-template <int OCC, int ENG>
-__global__ __launch_bounds__(WG_THREADS, OCC) void xcorr4_wg_kernel(WgArgs a)
+// Two workgroups per CU (launch bounds 256 threads x 2): each one's barrier
+// and LDS latency is covered by the other's MFMAs.
+template <int ENG, int IN_BITS>
+__global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
 {
-    static_assert(ENG == ENG_I8 || OCC == 2, "the FP8 engine runs at occupancy 2");
+    static_assert(ENG == ENG_I8 || IN_BITS == 4, "the FP8 engine takes 4-bit input");
+    typedef WgGeom<IN_BITS> Geo;
+    static_assert(Geo::TKS * Geo::ROWB == WG_STAGE, "stage size");
     typedef typename std::conditional<ENG == ENG_F8, f32x16, i32x16>::type AccT;
-    constexpr int WG_NBUF = OCC == 1 ? 8 : 4;   // LDS ring depth (stages)
     __shared__ __attribute__((aligned(16))) uint8_t lds[WG_NBUF * WG_STAGE];
 
     const int tid = threadIdx.x;
@@ -279,6 +336,7 @@ __global__ __launch_bounds__(WG_THREADS, OCC) void xcorr4_wg_kernel(WgArgs a)
     };
     const uint32_t lds_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)lds;
     constexpr uint32_t OOR = 0x80000000u;
+    constexpr int TKS = Geo::TKS;
 
     // ---- copy cursor (every thread follows the same sequence of stages)
     int d_item = it_begin, d_stage = 0, d_nstage = 0, d_tcount = 0;
@@ -291,26 +349,27 @@ __global__ __launch_bounds__(WG_THREADS, OCC) void xcorr4_wg_kernel(WgArgs a)
         const int f = (int)(w.cs & 0xFFFFFFu);
         const int bi = (int)(w.ij & 0xFFFFu), bj = (int)(w.ij >> 16);
         const int N = sb.n_inputs;
-        d_rowstride = (uint32_t)sb.n_chans * (uint32_t)N;
+        d_rowstride = (uint32_t)sb.n_chans * (uint32_t)N * Geo::BPS;
         d_tcount = sb.t_count;
-        d_nstage = (sb.t_count + TK - 1) / TK;
-        d_base = sb.samples + ((size_t)sb.t_begin * sb.n_chans + f) * (size_t)N;
+        d_nstage = (sb.t_count + TKS - 1) / TKS;
+        d_base = sb.samples + ((size_t)sb.t_begin * sb.n_chans + f) * (size_t)N * Geo::BPS;
         const bool diag = bi == bj;
 #pragma unroll
         for (int k = 0; k < WG_DMA; ++k) {
             const int P = k * WG_THREADS + tid;  // 16-byte position in the stage
-            const int tau = P >> 4, slot = P & 15;
-            const int c = wg_chunk(tau, slot);
-            const int in = c < 8 ? 128 * bi + 16 * c : 128 * bj + 16 * (c - 8);
+            const int tau = P / Geo::NCH, sl = P % Geo::NCH;
+            const int c = Geo::chunk(tau, sl);
+            const int hc = Geo::NCH / 2;
+            const int in = c < hc ? 128 * bi + Geo::CIN * c : 128 * bj + Geo::CIN * (c - hc);
             // a diagonal tile reads its J operands from the I half
-            const bool on = in < N && !(diag && c >= 8);
-            d_voff[k] = on ? (uint32_t)tau * d_rowstride + (uint32_t)in : OOR;
+            const bool on = in < N && !(diag && c >= hc);
+            d_voff[k] = on ? (uint32_t)tau * d_rowstride + (uint32_t)(in * Geo::BPS) : OOR;
         }
     };
     int issued = 0;
     auto d_issue = [&]() {
-        const int t_first = d_stage * TK;
-        const int nt = d_tcount - t_first < TK ? d_tcount - t_first : TK;
+        const int t_first = d_stage * TKS;
+        const int nt = d_tcount - t_first < TKS ? d_tcount - t_first : TKS;
         const uint64_t base = (uint64_t)(uintptr_t)(d_base + (size_t)t_first * d_rowstride);
         const i32x4 rsrc = {(int)(uint32_t)base, (int)((uint32_t)(base >> 32) & 0xFFFFu),
                             (int)((uint32_t)nt * d_rowstride), 0x00020000};
@@ -328,34 +387,34 @@ __global__ __launch_bounds__(WG_THREADS, OCC) void xcorr4_wg_kernel(WgArgs a)
     int n_total = 0;
     for (int it = it_begin; it < it_end; ++it) {
         const WgSub &sb = a.subs[item_at(it).cs >> 24];
-        n_total += (sb.t_count + TK - 1) / TK;
+        n_total += (sb.t_count + TKS - 1) / TKS;
     }
     d_setup(it_begin);
 #pragma unroll
     for (int k = 0; k < WG_NBUF - 1; ++k)
         if (issued < n_total) d_issue();
 
-    // This wave's 64 x 64 quarter of tile w: I chunks ic.., J chunks jc.. of
-    // the staged row, output origin (r0, c0). On a diagonal tile the J half
-    // is not copied (J = I): waves 0, 1 take the diagonal quarters, wave 2
-    // the lower off-diagonal quarter, and wave 3 repeats wave 2's work
-    // without writing it.
-    auto role = [&](const WgItem &w, int &ic, int &jc, int &r0, int &c0, bool &write) {
+    // This wave's 64 x 64 quarter of tile w: its I inputs start at position
+    // ip, its J inputs at jp of the staged row (J half at 128), output origin
+    // (r0, c0). On a diagonal tile the J half is not copied (J = I): waves 0,
+    // 1 take the diagonal quarters, wave 2 the lower off-diagonal quarter,
+    // and wave 3 repeats wave 2's work without writing it.
+    auto role = [&](const WgItem &w, int &ip, int &jp, int &r0, int &c0, bool &write) {
         const int bi = (int)(w.ij & 0xFFFFu), bj = (int)(w.ij >> 16);
         const int I0 = 128 * bi, J0 = 128 * bj;
         write = true;
         if (bi != bj) {
             const int wr = wave >> 1, wc = wave & 1;
-            ic = 4 * wr;
-            jc = 8 + 4 * wc;
+            ip = 64 * wr;
+            jp = 128 + 64 * wc;
             r0 = I0 + 64 * wr;
             c0 = J0 + 64 * wc;
         } else if (wave < 2) {
-            ic = jc = 4 * wave;
+            ip = jp = 64 * wave;
             r0 = c0 = I0 + 64 * wave;
         } else {
-            ic = 4;
-            jc = 0;
+            ip = 64;
+            jp = 0;
             r0 = I0 + 64;
             c0 = I0;
             write = wave == 2;
@@ -363,46 +422,54 @@ __global__ __launch_bounds__(WG_THREADS, OCC) void xcorr4_wg_kernel(WgArgs a)
     };
 
     // ---- read cursor: the stage whose fragments are read next, and the
-    // transpose-load offsets of its tile's role
-    // Row tau = 32 k + 8 i + (16 (G >> 1) + m) of load (k, i) differs from
-    // the lane's base row by a multiple of 8, so its slot swizzle (tau & 7 =
-    // m) is the base row's: one register per (side, block), and the
-    // 8192 k + 2048 i parts are immediate offsets.
-    const int G = lane >> 4, m = (lane >> 1) & 7, h = lane & 1;
-    int fo[2][2]; // (side, block) -> byte offset of load (0, 0) in a stage
+    // transposing-load offsets of its tile's role. The rows of the loads of
+    // one (side, block) differ by multiples of 8 (4-bit) or 4 (8-bit) from
+    // the lane's base row, so they share its slot swizzle: one register per
+    // (side, block), the rest are immediate offsets.
+    const int G = lane >> 4;
+    int fo[2][2]; // (side, block) -> byte offset of load 0 in a stage
     int r_item = it_begin, r_stage = 0, r_nstage = 0, r_tcount = 0;
     auto r_setup = [&](int it) {
         const WgItem w = item_at(it);
         const WgSub &sb = a.subs[w.cs >> 24];
         r_tcount = sb.t_count;
-        r_nstage = (sb.t_count + TK - 1) / TK;
-        int ic, jc, r0, c0;
+        r_nstage = (sb.t_count + TKS - 1) / TKS;
+        int ip, jp, r0, c0;
         bool write;
-        role(w, ic, jc, r0, c0, write);
+        role(w, ip, jp, r0, c0, write);
 #pragma unroll
         for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
             for (int blk = 0; blk < 2; ++blk) {
-                const int tau = 16 * (G >> 1) + m;
-                const int c = (sd == 0 ? ic : jc) + 2 * blk + (G & 1);
-                fo[sd][blk] = tau * WG_ROWB + 16 * wg_slot(tau, c) + 8 * h;
+                const int pos = (sd == 0 ? ip : jp) + 32 * blk + 16 * (G & 1);
+                if constexpr (IN_BITS == 4) {
+                    const int m = (lane >> 1) & 7, h = lane & 1;
+                    const int tau = 16 * (G >> 1) + m;
+                    const int c = pos / Geo::CIN;
+                    fo[sd][blk] = tau * Geo::ROWB + 16 * Geo::slot(tau, c) + 8 * h;
+                } else {
+                    const int m = (lane >> 2) & 3, q = lane & 3;
+                    const int tau = 16 * (G >> 1) + m;
+                    const int c = pos / Geo::CIN + (q >> 1);
+                    fo[sd][blk] = tau * Geo::ROWB + 16 * Geo::slot(tau, c) + 8 * (q & 1);
+                }
             }
     };
 
     // Make the read cursor's stage s visible to every wave: this wave's
     // copies of it are done once at most the later issued stages are
     // outstanding; then barrier. Rows past the end of the segment are
-    // cleared cooperatively. Advances the read cursor.
+    // cleared cooperatively.
     auto prep_stage = [&](int s) {
         const int later = issued - (s + 1);
         if (later >= WG_NBUF - 2) wg_wait_barrier(WG_NBUF - 2);
         else if (later >= 1) wg_wait_barrier(1);
         else wg_wait_barrier(0);
-        const int nt = r_tcount - r_stage * TK;
-        if (nt < TK) {
+        const int nt = r_tcount - r_stage * TKS;
+        if (nt < TKS) {
             uint8_t *b = lds + (s % WG_NBUF) * WG_STAGE;
             for (int o = tid * 16; o < WG_STAGE; o += WG_THREADS * 16)
-                if (o / WG_ROWB >= nt) *(u32x4 *)(b + o) = u32x4{0u, 0u, 0u, 0u};
+                if (o / Geo::ROWB >= nt) *(u32x4 *)(b + o) = u32x4{0u, 0u, 0u, 0u};
             asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
         }
     };
@@ -421,29 +488,36 @@ __global__ __launch_bounds__(WG_THREADS, OCC) void xcorr4_wg_kernel(WgArgs a)
 #pragma unroll
                 for (int blk = 0; blk < 2; ++blk)
 #pragma unroll
-                    for (int i = 0; i < 2; ++i)
-                        R[k][sd][blk][i] = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
-                            (lds_i32x2 *)(b + fo[sd][blk] + (32 * k + 8 * i) * WG_ROWB));
+                    for (int i = 0; i < 2; ++i) {
+                        if constexpr (IN_BITS == 4) {
+                            // K step k, rows 8 i apart
+                            R[k][sd][blk][i] = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
+                                (lds_i32x2 *)(b + fo[sd][blk] + (32 * k + 8 * i) * Geo::ROWB));
+                        } else {
+                            // load 2 k + i, rows 4 (2 k + i) apart
+                            R[k][sd][blk][i] = (i32x2)__builtin_amdgcn_ds_read_tr16_b64_v4i16(
+                                (lds_i16x4 *)(b + fo[sd][blk] + 4 * (2 * k + i) * Geo::ROWB));
+                        }
+                    }
     };
 
     AccT accR[2][2], accI[2][2];
-    WgRaw RA, RB;
-    WgOps O0, O1;
+    WgRaw RA;
+    WgOps O0;
     r_setup(it_begin);
     prep_stage(0);
     read_frags(0, RA);
     r_advance();
-    if constexpr (ENG == ENG_I8) wg_unpack(RA, 0, O0);
     int s = 0; // global index of the stage being multiplied
 
     for (int it = it_begin; it < it_end; ++it) {
         const WgItem w = item_at(it);
         const WgSub &sb = a.subs[w.cs >> 24];
         const int f = (int)(w.cs & 0xFFFFFFu);
-        const int nst = (sb.t_count + TK - 1) / TK;
-        int ic, jc, r0, c0;
+        const int nst = (sb.t_count + TKS - 1) / TKS;
+        int ip, jp, r0, c0;
         bool write;
-        role(w, ic, jc, r0, c0, write);
+        role(w, ip, jp, r0, c0, write);
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -451,50 +525,25 @@ __global__ __launch_bounds__(WG_THREADS, OCC) void xcorr4_wg_kernel(WgArgs a)
                 accR[x][y] = AccT{};
                 accI[x][y] = AccT{};
             }
-        if constexpr (OCC == 1) {
-            for (int k = 0; k < nst; ++k, ++s) {
-                if (issued < n_total) d_issue();
-                if (s + 1 < n_total) prep_stage(s + 1);
-                // one basic block: read the next stage's fragments (after the
-                // last stage they are stale and unused) and interleave each K
-                // step's MFMAs with the unpack of the next K step
-                read_frags((s + 1) % WG_NBUF, RB);
-                wg_unpack(RA, 1, O1);
+        // the stage's fragments were read by the previous step (RA); unpack
+        // and multiply, then publish and read the next stage
+        for (int k = 0; k < nst; ++k, ++s) {
+            if (issued < n_total) d_issue();
+            if constexpr (ENG == ENG_F8) {
+                wg_f8_stage(RA, accR, accI);
+            } else if constexpr (IN_BITS == 4) {
+                wg_unpack(RA, 0, O0);
                 wg_mfma(O0, accR, accI);
-                wg_unpack(RB, 0, O0);
-                wg_mfma(O1, accR, accI);
-#pragma unroll
-                for (int sd = 0; sd < 2; ++sd)
-#pragma unroll
-                    for (int blk = 0; blk < 2; ++blk)
-#pragma unroll
-                        for (int i = 0; i < 2; ++i) RA[1][sd][blk][i] = RB[1][sd][blk][i];
-                __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);
-#pragma unroll
-                for (int q = 0; q < 32; ++q) {
-                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
-                }
-                if (s + 1 < n_total) r_advance();
+                wg_unpack(RA, 1, O0);
+                wg_mfma(O0, accR, accI);
+            } else {
+                wg8_unpack(RA, O0);
+                wg_mfma(O0, accR, accI);
             }
-        } else {
-            // the stage's fragments were read by the previous step (RA); unpack
-            // and multiply one K step at a time, then publish and read the next
-            for (int k = 0; k < nst; ++k, ++s) {
-                if (issued < n_total) d_issue();
-                if constexpr (ENG == ENG_I8) {
-                    wg_unpack(RA, 0, O0);
-                    wg_mfma(O0, accR, accI);
-                    wg_unpack(RA, 1, O0);
-                    wg_mfma(O0, accR, accI);
-                } else {
-                    wg_f8_stage(RA, accR, accI);
-                }
-                if (s + 1 < n_total) {
-                    prep_stage(s + 1);
-                    read_frags((s + 1) % WG_NBUF, RA);
-                    r_advance();
-                }
+            if (s + 1 < n_total) {
+                prep_stage(s + 1);
+                read_frags((s + 1) % WG_NBUF, RA);
+                r_advance();
             }
         }
 
@@ -538,8 +587,8 @@ __global__ __launch_bounds__(WG_THREADS, OCC) void xcorr4_wg_kernel(WgArgs a)
                     for (int e = 0; e < 4; ++e)
 #pragma unroll
                         for (int y = 0; y < 2; ++y) {
-                            const u32x2 v = {old[e][y].x + acc_word(accR[x][y][4 * q + e]),
-                                             old[e][y].y + acc_word(accI[x][y][4 * q + e])};
+                            const u32x2 v = {old[e][y].x + acc_word<IN_BITS>(accR[x][y][4 * q + e]),
+                                             old[e][y].y + acc_word<IN_BITS>(accI[x][y][4 * q + e])};
                             __builtin_amdgcn_raw_buffer_store_b64(v, vrs, (int)off[e][y], 0, 0);
                         }
                 } else {
@@ -547,8 +596,8 @@ __global__ __launch_bounds__(WG_THREADS, OCC) void xcorr4_wg_kernel(WgArgs a)
                     for (int e = 0; e < 4; ++e)
 #pragma unroll
                         for (int y = 0; y < 2; ++y) {
-                            const u32x2 v = {acc_word(accR[x][y][4 * q + e]),
-                                             acc_word(accI[x][y][4 * q + e])};
+                            const u32x2 v = {acc_word<IN_BITS>(accR[x][y][4 * q + e]),
+                                             acc_word<IN_BITS>(accI[x][y][4 * q + e])};
                             __builtin_amdgcn_raw_buffer_store_b64(v, vrs, (int)off[e][y], 0, 0);
                         }
                 }

@@ -51,9 +51,7 @@ int fail(int code, const char *fmt, ...)
     } while (0)
 
 constexpr int MAX_SUBS = 16;        // subarrays per context (kernel-argument descriptors)
-#ifndef WG_OCC
-#define WG_OCC 2                    // workgroups per CU of the persistent kernel
-#endif
+constexpr int WG_PER_CU = 2;        // resident workgroups per CU of the persistent kernel
 
 struct Sub {
     xeng_subarray cfg{};
@@ -71,6 +69,7 @@ struct Sub {
 // One persistent-kernel launch group: the subarrays it covers and its schedule.
 struct WavePlan {
     int engine = XENG_ENGINE_I8;     // every subarray of a plan uses this engine
+    int in_bits = 4;                 // and this input width
     std::vector<int> subs;           // context subarray indices, in launch order
     std::vector<xeng::WgItem> items; // flat, grouped per workgroup
     std::vector<int32_t> wg_begin;   // [n_wg + 1]
@@ -112,7 +111,11 @@ KernelFn pick_kernel(int in_bits, int wt, int n_inputs)
     return (n_inputs % 2 == 0) ? pick_wt<8, true>(wt) : pick_wt<8, false>(wt);
 }
 
-bool wave_path(const xeng_subarray &c) { return c.in_bits == 4 && c.n_inputs % 16 == 0; }
+// Persistent-workgroup kernel: 16-byte copy chunks of whole inputs.
+bool wave_path(const xeng_subarray &c)
+{
+    return (c.in_bits == 4 && c.n_inputs % 16 == 0) || (c.in_bits == 8 && c.n_inputs % 8 == 0);
+}
 
 int choose_wt(int n_inputs)
 {
@@ -171,7 +174,8 @@ void build_schedule(WavePlan &p, const std::vector<Sub> &subs, int n_cu)
     for (size_t k = 0; k < p.subs.size(); ++k) {
         const Sub &s = subs[p.subs[k]];
         const int nb = (s.cfg.n_inputs + 127) / 128;
-        const int nst = (s.cfg.n_time + xeng::TK - 1) / xeng::TK;
+        const int tks = s.cfg.in_bits == 4 ? xeng::WgGeom<4>::TKS : xeng::WgGeom<8>::TKS;
+        const int nst = (s.cfg.n_time + tks - 1) / tks;
         const int segs = (s.cfg.n_time + xeng::SEG_T - 1) / xeng::SEG_T;
         const double per_stage = (double)nst / segs;
         for (int f = 0; f < s.cfg.n_chans; ++f)
@@ -187,7 +191,7 @@ void build_schedule(WavePlan &p, const std::vector<Sub> &subs, int n_cu)
                 }
     }
     const int64_t n_items = (int64_t)all.size();
-    const int n_wg = (int)std::min<int64_t>((int64_t)n_cu * WG_OCC, n_items);
+    const int n_wg = (int)std::min<int64_t>((int64_t)n_cu * WG_PER_CU, n_items);
     p.n_wg = n_wg;
     std::vector<std::vector<int>> xwg(8);
     for (int b = 0; b < n_wg; ++b) xwg[b % 8].push_back(b);
@@ -299,10 +303,13 @@ int launch_wave(xeng_ctx *ctx, WavePlan &p, const void *const *d_samples)
         a.items = p.d_items;
         a.wg_begin = p.d_wg_begin;
         if (p.engine == XENG_ENGINE_FP8)
-            hipLaunchKernelGGL((xeng::xcorr4_wg_kernel<2, xeng::ENG_F8>), dim3(p.n_wg),
+            hipLaunchKernelGGL((xeng::xcorr_wg_kernel<xeng::ENG_F8, 4>), dim3(p.n_wg),
+                               dim3(xeng::WG_THREADS), 0, ctx->stream, a);
+        else if (p.in_bits == 4)
+            hipLaunchKernelGGL((xeng::xcorr_wg_kernel<xeng::ENG_I8, 4>), dim3(p.n_wg),
                                dim3(xeng::WG_THREADS), 0, ctx->stream, a);
         else
-            hipLaunchKernelGGL((xeng::xcorr4_wg_kernel<WG_OCC, xeng::ENG_I8>), dim3(p.n_wg),
+            hipLaunchKernelGGL((xeng::xcorr_wg_kernel<xeng::ENG_I8, 8>), dim3(p.n_wg),
                                dim3(xeng::WG_THREADS), 0, ctx->stream, a);
         HIP_TRY(hipGetLastError());
         for (int k : p.subs) ctx->subs[k].acc_zero = false;
@@ -395,27 +402,27 @@ int xeng_create(const xeng_subarray *subs, int n_subs, void *hip_stream, xeng_ct
         }
         if (s.wave) wave_subs.push_back(k);
     }
-    // per engine: one launch group for all its wave-path subarrays when each
-    // fits one segment; otherwise one group per subarray
-    for (int eng : {XENG_ENGINE_I8, XENG_ENGINE_FP8}) {
+    // per (engine, input width): one launch group for all its wave-path
+    // subarrays when each fits one segment; otherwise one group per subarray
+    const int kinds[3][2] = {{XENG_ENGINE_I8, 4}, {XENG_ENGINE_I8, 8}, {XENG_ENGINE_FP8, 4}};
+    for (const auto &kd : kinds) {
         std::vector<int> es;
         bool one_group = true;
         for (int k : wave_subs)
-            if (ctx->subs[k].cfg.engine == eng) {
+            if (ctx->subs[k].cfg.engine == kd[0] && ctx->subs[k].cfg.in_bits == kd[1]) {
                 es.push_back(k);
                 if (ctx->subs[k].cfg.n_time > xeng::SEG_T) one_group = false;
             }
         if (es.empty()) continue;
-        if (one_group) {
+        std::vector<std::vector<int>> groups;
+        if (one_group) groups.push_back(es);
+        else
+            for (int k : es) groups.push_back({k});
+        for (auto &g : groups) {
             ctx->plans.emplace_back();
-            ctx->plans.back().engine = eng;
-            ctx->plans.back().subs = es;
-        } else {
-            for (int k : es) {
-                ctx->plans.emplace_back();
-                ctx->plans.back().engine = eng;
-                ctx->plans.back().subs = {k};
-            }
+            ctx->plans.back().engine = kd[0];
+            ctx->plans.back().in_bits = kd[1];
+            ctx->plans.back().subs = g;
         }
     }
     for (WavePlan &p : ctx->plans) {

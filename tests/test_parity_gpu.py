@@ -180,3 +180,37 @@ def test_several_subarrays_one_context(torch_cuda, oracle_lib):
         acc = oracle_lib.correlate(x, b)
         want = oracle_lib.narrow(acc * 2)
         assert np.array_equal(got, want), (N, F, T, b)
+
+
+@pytest.mark.parametrize("code", [-128, 127])
+def test_extreme_values_8bit_direct_path(torch_cuda, oracle_lib, code):
+    # N a multiple of 8: the 8-bit stream goes through the LDS-copy kernel
+    print("case 8-bit extremes N=72 code=%d" % code, flush=True)
+    s = np.full((300, 2, 72, 2), code, np.int8)
+    want = oracle_lib.narrow(oracle_lib.correlate(s, 8))
+    assert np.array_equal(gpu_once(torch_cuda, s, 8), want)
+
+
+def test_8bit_multi_segment(torch_cuda, oracle_lib):
+    # two launch segments of 8-bit input, sums up to the 8-bit dump bound's scale
+    print("case 8-bit multi-segment", flush=True)
+    rng = np.random.default_rng(97)
+    s = rand_stream(rng, 40000, 2, 24, 8)
+    want = oracle_lib.narrow(oracle_lib.correlate(s, 8))
+    assert np.array_equal(gpu_once(torch_cuda, s, 8), want)
+
+
+def test_int8_variant_sampled_channels(torch_cuda, oracle_lib):
+    # full-size 8-bit precision workload (N=512, 256 channels, 16384 samples,
+    # sigma 20): 4 seeded-random channels against the oracle in full, 8 more
+    # by the projection check
+    print("case int8_variant full size", flush=True)
+    s, _, _, meta = synth.workload("int8_variant")
+    got = gpu_once(torch_cuda, s, 8)
+    rng = np.random.default_rng(2026)
+    chans = sorted(rng.choice(256, 12, replace=False).tolist())
+    want = oracle_lib.narrow(oracle_lib.correlate(s, 8, chans=chans[:4]))
+    assert np.array_equal(got[chans[:4]], want)
+    for f in chans[4:]:
+        w = rng.integers(-4, 5, size=(512, 2)).astype(np.int64)
+        assert oracle_lib.projection_check(s, 8, int(f), got[f], w) == 0
