@@ -99,6 +99,179 @@ def cpu_baseline(samples, n_inputs, n_chans, n_time, in_bits=4, budget_s=15.0):
             "cmac_per_s": cmac / dt}
 
 
+STREAM_CFG = dict(n_inputs=512, n_chans=2400, n_time=8192, in_bits=4)  # 2400 x 24 kHz, 0.341 s gulps
+
+
+def stream_bench(args):
+    """Real-time streaming: a continuous 4-bit stream (drifting common tone)
+    produced on the device gulp by gulp into a 4-slot ring, integrated and
+    dumped every 26 gulps. Reports sustained Tops/s and real-time factor
+    (unpaced), per-gulp latency percentiles (gulps injected at a fixed rate),
+    and checks one dump period against the oracle."""
+    import numpy as np
+    import torch
+
+    import synth
+    import synth.gpu
+    from paper_1411_3751_amd import Stream
+
+    torch.cuda.set_device(0)
+    synth.gpu.build()
+    N, F, T = STREAM_CFG["n_inputs"], STREAM_CFG["n_chans"], STREAM_CFG["n_time"]
+    every, slots = args.dump_every, 4
+    seed = synth.SEED_BASE + 4
+    tone = (synth.TONE_AMP, lambda t: synth.drift_phase(t, T), synth.tone_channels(F))
+    n_max = max(args.stream_gulps + 8, every)
+    gen = synth.gpu.DeviceStream(seed, F, N, 4, 2.5, tone=tone, t_total=n_max * T)
+    tri = N * (N + 1) // 2
+    cmac_gulp = F * tri * T
+    gulp_s = T / CHANNEL_HZ
+    hd = [torch.empty((F, tri, 2), dtype=torch.int32, pin_memory=True) for _ in range(2)]
+    sub = dict(STREAM_CFG)
+    res = {}
+
+    def feed(st, g0, n, pace_s=0.0):
+        t_next = time.perf_counter()
+        for g in range(g0, g0 + n):
+            if pace_s:
+                while time.perf_counter() < t_next:
+                    time.sleep(0.0005)
+                t_next += pace_s
+            ptr, ist = st.next_slot()
+            gen.fill(ptr, g * T, T, ist)
+            st.push()
+
+    # 1. one dump period, checked against the oracle (sampled channels)
+    log("stream: verification period (%d gulps) ..." % every)
+    with Stream(sub, n_slots=slots, dump_every=every, host_dumps=hd) as st:
+        feed(st, 0, every)
+        st.dump_wait(0)
+        got = hd[0].numpy().copy()
+    rng = np.random.default_rng(55)
+    tch = synth.tone_channels(F)
+    chans = tch + sorted(rng.choice([f for f in range(F) if f not in tch], 4, replace=False).tolist())
+    proj = sorted(rng.choice([f for f in range(F) if f not in chans], 8, replace=False).tolist())
+    import oracle
+    oracle.build(force=False)
+    x, _, _ = synth.stream(seed, every * T, F, N, 4, 2.5, chans=chans + proj, tone=tone)
+    xs = np.ascontiguousarray(x[:, :len(chans)])
+    want = oracle.narrow(oracle.correlate(xs, 4))
+    exact = bool(np.array_equal(got[chans], want))
+    proj_ok = True
+    for k, f in enumerate(proj):
+        w = rng.integers(-4, 5, size=(N, 2)).astype(np.int64)
+        xp = np.ascontiguousarray(x[:, len(chans) + k:len(chans) + k + 1])
+        proj_ok &= oracle.projection_check(xp, 4, 0, got[f], w) == 0
+    del x, xs
+    res["dump0_exact_channels"] = chans
+    res["dump0_exact"] = exact
+    res["dump0_projection_channels"] = proj
+    res["dump0_projection_ok"] = bool(proj_ok)
+    log("stream: dump 0 exact on %d channels: %s, projection on %d: %s" % (
+        len(chans), exact, len(proj), proj_ok))
+
+    # 2. unpaced: sustained throughput and real-time factor
+    n = args.stream_gulps
+    with Stream(sub, n_slots=slots, dump_every=every, host_dumps=hd) as st:
+        feed(st, 0, 2 * slots)          # warm-up gulps (not timed)
+        st.gulp_times(2 * slots - 1)
+        t0 = time.perf_counter()
+        feed(st, 2 * slots, n)
+        st.gulp_times(2 * slots + n - 1)
+        wall = time.perf_counter() - t0
+    res["sustained_tops"] = cmac_gulp * n * OPS_PER_CMAC / wall / 1e12
+    res["rtf"] = n * gulp_s / wall
+    res["gulps_timed"] = n
+    log("stream: %d gulps in %.2f s: %.1f Tops/s, RTF %.1f" % (n, wall, res["sustained_tops"],
+                                                              res["rtf"]))
+
+    # 3. paced: gulps arrive every gulp_s / pace seconds; latency percentiles
+    pace = args.pace
+    with Stream(sub, n_slots=slots, dump_every=every, host_dumps=hd) as st:
+        feed(st, 0, n, pace_s=gulp_s / pace)
+        lat = [st.gulp_times(g) for g in range(n)]
+    arr = np.array([a for a, _ in lat])
+    rdy = np.array([r for _, r in lat])
+    xe = float(np.percentile(rdy, 50))
+    res.update({
+        "xengine_gulp_ms_p50": xe,
+        "xengine_tops_p50": cmac_gulp * OPS_PER_CMAC / (xe * 1e-3) / 1e12,
+        "xengine_rtf_p50": gulp_s / (xe * 1e-3),
+        "pace_x_realtime": pace,
+        "gulp_ms_p50": float(np.percentile(rdy, 50)), "gulp_ms_p99": float(np.percentile(rdy, 99)),
+        "gulp_ms_max": float(rdy.max()),
+        "ingest_gulp_ms_p50": float(np.percentile(arr, 50)),
+        "ingest_gulp_ms_p99": float(np.percentile(arr, 99)),
+    })
+    out = {
+        "metric": METRIC, "value": round(res["sustained_tops"], 2), "unit": "Tops/s",
+        "n_gpus": 1, "steps": n, "warmup": 2 * slots, "ms_per_step": round(1e3 * gulp_s / res["rtf"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": "stream_2400ch", "n_inputs": N, "n_chans": F, "n_time": T,
+                   "in_bits": 4, "engine": "i8", "ring_slots": slots, "dump_every": every,
+                   "ingest": "device generator (counter-based, drifting tone)"},
+    }
+    out.update({k: (round(v, 3) if isinstance(v, float) else v) for k, v in res.items()})
+    print(json.dumps(out), flush=True)
+
+
+def batch_bench(args):
+    """Batched subarrays of uneven N (64 ... 2048 inputs, 4096 samples each):
+    autotuned kernel choices, one persistent launch per engine and input
+    width, the whole step (correlate + dump) captured in a HIP graph and
+    replayed."""
+    import torch
+
+    import synth
+    from paper_1411_3751_amd import Correlator
+
+    torch.cuda.set_device(0)
+    subs, dev, cmac = [], [], 0
+    for k in range(len(synth.BATCH_SHAPES)):
+        x, _, _, meta = synth.workload("batch", subarray=k)
+        N, F, T = meta["n_inputs"], meta["n_chans"], meta["n_time"]
+        subs.append(dict(n_inputs=N, n_chans=F, n_time=T))
+        dev.append(torch.from_numpy(x).cuda())
+        cmac += F * N * (N + 1) // 2 * T
+    out = [torch.empty((d["n_chans"], d["n_inputs"] * (d["n_inputs"] + 1) // 2, 2),
+                       dtype=torch.int32, device="cuda") for d in subs]
+    stream = torch.cuda.current_stream()
+    with Correlator(subs, stream=stream) as c:
+        t0 = time.perf_counter()
+        c.autotune(dev, reps=3)
+        tune_s = time.perf_counter() - t0
+        plan = c.plan()
+        log("plan:", json.dumps(plan))
+        with c.capture(dev, out) as g:
+            for _ in range(args.warmup):
+                g.launch(stream)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                g.launch(stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+    value = cmac * OPS_PER_CMAC / (ms * 1e-3) / 1e12
+    res = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Tops/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": "batch_uneven", "subarrays": [[d["n_inputs"], d["n_chans"]] for d in subs],
+                   "n_time": subs[0]["n_time"], "in_bits": 4, "engine": "i8",
+                   "step": "graph replay: correlate + dump"},
+        "pct_int8_peak": round(100.0 * value / (PEAK_INT8_OPS / 1e12), 2),
+        "autotune_s": round(tune_s, 2),
+        "choices": [[s["n_inputs"], s["kernel"], s.get("tile")] for s in plan["subarrays"]],
+        "schedule": [plan["workgroups_per_cu"], plan["schedule_order"]],
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,7 +287,29 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (3 times), the "
                          "reference for scaling HBM byte counters, and exit")
+    ap.add_argument("--stream", action="store_true",
+                    help="run the real-time streaming configuration instead (N=512, 2400 "
+                         "channels, 8192-sample gulps, 4-slot ring)")
+    ap.add_argument("--batch", action="store_true",
+                    help="run the batched uneven-subarray configuration instead (autotuned, "
+                         "graph-captured)")
+    ap.add_argument("--stream-gulps", type=int, default=260)
+    ap.add_argument("--dump-every", type=int, default=26)
+    ap.add_argument("--pace", type=float, default=4.0,
+                    help="latency run: gulps arrive at this multiple of the real-time rate")
     args = ap.parse_args()
+    if args.batch:
+        if args.gpus != 1:
+            print("bench.py measures one GPU (--gpus %d requested)" % args.gpus, file=sys.stderr)
+            sys.exit(2)
+        batch_bench(args)
+        return
+    if args.stream:
+        if args.gpus != 1:
+            print("bench.py measures one GPU (--gpus %d requested)" % args.gpus, file=sys.stderr)
+            sys.exit(2)
+        stream_bench(args)
+        return
     if args.copy_calibration:
         import torch
         n = args.copy_calibration << 20

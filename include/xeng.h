@@ -129,6 +129,110 @@ int xeng_max_dump_samples(const xeng_ctx *ctx, int sub, int64_t *out);
  */
 int xeng_plan_describe(const xeng_ctx *ctx, char *buf, size_t len);
 
+/*
+ * ---- Autotuning and graph capture (batched subarrays of uneven N in one
+ * persistent launch per engine and input width).
+ *
+ * Time, on the caller's sample buffers d_samples[s] (as for xeng_correlate),
+ * every kernel family that can run each subarray (the persistent kernel with
+ * 128 x 128 tiles; the register-staging kernel with 32, 64 or 128-input
+ * tiles), each alone, `reps` runs each, and keep the fastest; then time the
+ * batched launch's schedule options (1 or 2 workgroups per CU, tiles in
+ * locality order or costliest first) and keep the fastest. The choices are
+ * applied to ctx and remembered for this process: later contexts with the
+ * same subarray shapes start with them. Any accumulated sums are discarded
+ * (the context is left reset). Blocks until done. Errors: XENG_EINVAL,
+ * XENG_EHIP.
+ */
+int xeng_autotune(xeng_ctx *ctx, const void *const *d_samples, int reps);
+
+typedef struct xeng_graph xeng_graph; /* opaque, library-owned */
+
+/*
+ * Capture one whole step into a HIP graph: xeng_correlate(d_samples), then
+ * xeng_dump(out, out_is_device = 1, reset = 1). The context must have nothing
+ * accumulated (a fresh or just-reset context; XENG_EINVAL otherwise) and is
+ * left so. Each xeng_graph_launch re-runs the step on the same buffers: the
+ * caller refills d_samples[s] and reads out[s] (device pointers) around the
+ * launches. The graph holds no memset nodes (buffers are cleared by
+ * kernels). The graph stays valid while ctx lives; do not interleave its
+ * launches with eager calls on ctx without ordering them on one stream.
+ */
+int xeng_graph_create(xeng_ctx *ctx, const void *const *d_samples, void *const *out,
+                      xeng_graph **out_graph);
+
+/* Enqueue one replay of the captured step on hip_stream (a hipStream_t). */
+int xeng_graph_launch(xeng_graph *g, void *hip_stream);
+
+/* Release a graph. NULL is a no-op. */
+int xeng_graph_destroy(xeng_graph *g);
+
+/*
+ * ---- Streaming integration (Section 2.5: spectra arrive in groups that are
+ * cross-multiplied and summed until the dump cadence; Section 2.4: the data
+ * reach the GPU through ring buffers).
+ *
+ * A stream owns a device ring of n_slots gulps (each n_time samples of one
+ * subarray, in the subarray's input layout), a context that integrates them,
+ * and three HIP streams of default priority: ingest (fills slots), compute
+ * (correlates, dumps and resets) and output (copies dumps to the host).
+ * Every dump_every gulps the sums are dumped, copied to the caller's host
+ * buffers if given, and reset. Slot reuse, dump buffers and the host copies
+ * are ordered by events, so the host never blocks in next_slot/push unless a
+ * slot or dump buffer is still in use.
+ */
+typedef struct xeng_stream xeng_stream;
+
+/*
+ * Create a stream for one subarray on the current device. n_slots >= 2,
+ * dump_every >= 1 with dump_every * n_time within the subarray's dump limit.
+ * host_dumps: NULL (dumps stay on the device) or n_host_dumps >= 1 caller-
+ * owned host buffers of n_chans * N(N+1)/2 * 8 bytes, preferably pinned;
+ * dump d is written to host_dumps[d % n_host_dumps], where it stays until
+ * the push that completes dump d + n_host_dumps. Errors: XENG_EINVAL,
+ * XENG_ERANGE (dump period above the dump limit), XENG_ENOMEM, XENG_EHIP.
+ */
+int xeng_stream_create(const xeng_subarray *sub, int n_slots, int dump_every,
+                       void *const *host_dumps, int n_host_dumps, xeng_stream **out);
+
+/*
+ * Slot for the next gulp. Makes the ingest stream wait until the gulp that
+ * used the slot before has been correlated, records the gulp's arrival, and
+ * returns the slot's device pointer and the ingest stream (a hipStream_t).
+ * The caller enqueues the work that fills the slot (a copy, a producer
+ * kernel) on that stream and then calls xeng_stream_push. Calling it twice
+ * without a push returns the same slot.
+ */
+int xeng_stream_next_slot(xeng_stream *s, void **d_slot, void **ingest_stream);
+
+/*
+ * The slot from xeng_stream_next_slot is filled by the work enqueued on the
+ * ingest stream so far: enqueue its correlation on the compute stream and,
+ * when it completes a dump period, the dump, the host copy and the reset.
+ * Returns at once. *gulp (may be NULL) receives the gulp's index.
+ */
+int xeng_stream_push(xeng_stream *s, int64_t *gulp);
+
+/*
+ * Wait until dump d (0-based) is complete: in the caller's host buffer if
+ * host dumps were given, else in the device buffer whose pointer is stored
+ * in *d_dump (valid until dump d + 2 is written). d_dump may be NULL.
+ */
+int xeng_stream_dump_wait(xeng_stream *s, int64_t d, void **d_dump);
+
+/*
+ * Wait for gulp g (one of the last 4096 pushed) and report, in milliseconds,
+ * the time from its arrival (next_slot) and from its slot being filled to
+ * the end of its correlation (and of its dump, when it completes one).
+ */
+int xeng_stream_gulp_times(xeng_stream *s, int64_t g, float *arrive_ms, float *ready_ms);
+
+/* Number of gulps pushed so far. */
+int xeng_stream_gulps(const xeng_stream *s, int64_t *out);
+
+/* Wait for all work of the stream and release it. NULL is a no-op. */
+int xeng_stream_destroy(xeng_stream *s);
+
 /* Static text for an XENG_* code. */
 const char *xeng_strerror(int code);
 

@@ -7,6 +7,8 @@ from .xeng import (  # noqa: F401
     ENGINE_FP8,
     ENGINE_I8,
     Correlator,
+    Graph,
+    Stream,
     Subarray,
     XengError,
     load,

@@ -4,11 +4,13 @@
 // imaginary words hold Im V_ij - S_i, see xcorr_wg.h, and the dump kernel
 // turns them into Im V_ij), checks the exactness bounds before any launch,
 // splits each call into segments of at most SEG_T samples, and launches:
-//   - 4-bit subarrays with N a multiple of 16: the persistent-workgroup
-//     kernel, all such subarrays of the context in one launch over a
-//     precomputed, cost-balanced list of 128 x 128 tiles;
-//   - other subarrays (8-bit input, other N): the register-staging tile
-//     kernel, one launch per subarray and segment.
+//   - subarrays with N a multiple of 16 (4-bit) or 8 (8-bit): the
+//     persistent-workgroup kernel, all such subarrays of one engine and input
+//     width in one launch over a precomputed, cost-balanced list of
+//     128 x 128 tiles;
+//   - other subarrays: the register-staging tile kernel, one launch per
+//     subarray and segment.
+// The streaming ring (xeng_stream_*) is built on this API in xeng_stream.h.
 #include <hip/hip_runtime.h>
 
 #include <stdarg.h>
@@ -17,9 +19,12 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/xeng.h"
@@ -84,6 +89,9 @@ struct WavePlan {
 struct xeng_ctx {
     std::vector<Sub> subs;
     std::vector<WavePlan> plans;
+    int wg_per_cu = WG_PER_CU;       // persistent launches: workgroups per CU
+    int order = 0;                   // persistent schedule: 0 locality, 1 costliest first
+    bool tuned = false;              // choices came from the autotuner (or its cache)
     hipStream_t stream = nullptr;
     int device = 0;
     int n_cu = 0;
@@ -164,7 +172,7 @@ int validate(const xeng_subarray &s, int idx)
 // workgroup, so that the workgroups of an XCD work on neighbouring tiles (the
 // same channels, at the same times, whose rows they share in that XCD's L2);
 // inside a round the costliest tile goes to the least-loaded workgroup.
-void build_schedule(WavePlan &p, const std::vector<Sub> &subs, int n_cu)
+void build_schedule(WavePlan &p, const std::vector<Sub> &subs, int n_cu, int wg_per_cu, int order)
 {
     struct It {
         xeng::WgItem w;
@@ -190,8 +198,12 @@ void build_schedule(WavePlan &p, const std::vector<Sub> &subs, int n_cu)
                     all.push_back(it);
                 }
     }
+    // order 1: costliest tiles first (the list is still cut into contiguous
+    // per-XCD parts, which then hold similar-cost tiles)
+    if (order == 1)
+        std::stable_sort(all.begin(), all.end(), [](const It &a, const It &b) { return a.cost > b.cost; });
     const int64_t n_items = (int64_t)all.size();
-    const int n_wg = (int)std::min<int64_t>((int64_t)n_cu * WG_PER_CU, n_items);
+    const int n_wg = (int)std::min<int64_t>((int64_t)n_cu * wg_per_cu, n_items);
     p.n_wg = n_wg;
     std::vector<std::vector<int>> xwg(8);
     for (int b = 0; b < n_wg; ++b) xwg[b % 8].push_back(b);
@@ -329,14 +341,118 @@ int dump_device(const Sub &s, uint32_t *out, hipStream_t st)
     return XENG_OK;
 }
 
-void free_ctx(xeng_ctx *ctx)
+void free_plans(xeng_ctx *ctx)
 {
-    for (Sub &s : ctx->subs)
-        if (s.d_acc) (void)hipFree(s.d_acc);
     for (WavePlan &p : ctx->plans) {
         if (p.d_items) (void)hipFree(p.d_items);
         if (p.d_wg_begin) (void)hipFree(p.d_wg_begin);
     }
+    ctx->plans.clear();
+}
+
+// Launch groups of the persistent kernel from the subarrays' kernel choices:
+// per (engine, input width), one group for all its subarrays when each fits
+// one segment, otherwise one group per subarray.
+int replan(xeng_ctx *ctx)
+{
+    free_plans(ctx);
+    for (Sub &s : ctx->subs) {
+        const int nb = (s.cfg.n_inputs + s.bt - 1) / s.bt;
+        s.n_tiles = nb * (nb + 1) / 2;
+    }
+    const int kinds[3][2] = {{XENG_ENGINE_I8, 4}, {XENG_ENGINE_I8, 8}, {XENG_ENGINE_FP8, 4}};
+    for (const auto &kd : kinds) {
+        std::vector<int> es;
+        bool one_group = true;
+        for (int k = 0; k < (int)ctx->subs.size(); ++k) {
+            const Sub &s = ctx->subs[k];
+            if (s.wave && s.cfg.engine == kd[0] && s.cfg.in_bits == kd[1]) {
+                es.push_back(k);
+                if (s.cfg.n_time > xeng::SEG_T) one_group = false;
+            }
+        }
+        if (es.empty()) continue;
+        std::vector<std::vector<int>> groups;
+        if (one_group) groups.push_back(es);
+        else
+            for (int k : es) groups.push_back({k});
+        for (auto &g : groups) {
+            ctx->plans.emplace_back();
+            ctx->plans.back().engine = kd[0];
+            ctx->plans.back().in_bits = kd[1];
+            ctx->plans.back().subs = g;
+        }
+    }
+    for (WavePlan &p : ctx->plans) {
+        build_schedule(p, ctx->subs, ctx->n_cu, ctx->wg_per_cu, ctx->order);
+        int rc = upload_plan(p);
+        if (rc) return rc;
+    }
+    return XENG_OK;
+}
+
+// ---- tuning cache: choices found by xeng_autotune, per subarray shape and
+// per set of shapes (the schedule of a batched launch), for this process.
+struct SubKey {
+    int n, f, t, b, e;
+    bool operator<(const SubKey &o) const
+    {
+        return std::tie(n, f, t, b, e) < std::tie(o.n, o.f, o.t, o.b, o.e);
+    }
+};
+struct SubChoice {
+    bool wave;
+    int wt;
+};
+struct SchedChoice {
+    int wg_per_cu, order;
+};
+std::mutex g_tune_mu;
+std::map<SubKey, SubChoice> g_tune_sub;
+std::map<std::vector<SubKey>, SchedChoice> g_tune_sched;
+
+SubKey key_of(const xeng_subarray &c) { return SubKey{c.n_inputs, c.n_chans, c.n_time, c.in_bits, c.engine}; }
+
+std::vector<SubKey> keys_of(const xeng_ctx *ctx)
+{
+    std::vector<SubKey> v;
+    for (const Sub &s : ctx->subs) v.push_back(key_of(s.cfg));
+    return v;
+}
+
+void set_choice(Sub &s, bool wave, int wt)
+{
+    // the FP8 engine exists only in the persistent kernel
+    s.wave = wave_path(s.cfg) && (wave || s.cfg.engine == XENG_ENGINE_FP8);
+    s.wt = wt;
+    s.bt = 32 * wt;
+}
+
+void apply_tuning_cache(xeng_ctx *ctx)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    bool all = true;
+    for (Sub &s : ctx->subs) {
+        auto it = g_tune_sub.find(key_of(s.cfg));
+        if (it == g_tune_sub.end()) {
+            all = false;
+            continue;
+        }
+        set_choice(s, it->second.wave, it->second.wt);
+    }
+    auto it = g_tune_sched.find(keys_of(ctx));
+    if (it != g_tune_sched.end()) {
+        ctx->wg_per_cu = it->second.wg_per_cu;
+        ctx->order = it->second.order;
+    }
+    ctx->tuned = all && it != g_tune_sched.end();
+}
+
+void free_ctx(xeng_ctx *ctx)
+{
+    for (Sub &s : ctx->subs)
+        if (s.d_acc) (void)hipFree(s.d_acc);
+    free_plans(ctx);
     if (ctx->d_stage) (void)hipFree(ctx->d_stage);
     delete ctx;
 }
@@ -381,15 +497,12 @@ int xeng_create(const xeng_subarray *subs, int n_subs, void *hip_stream, xeng_ct
         return fail(XENG_EHIP, "cannot query the current HIP device");
     }
     ctx->subs.resize(n_subs);
-    std::vector<int> wave_subs;
     for (int k = 0; k < n_subs; ++k) {
         Sub &s = ctx->subs[k];
         s.cfg = subs[k];
         s.tri = (int64_t)s.cfg.n_inputs * (s.cfg.n_inputs + 1) / 2;
         s.max_dump = s.cfg.in_bits == 4 ? XENG_MAX_DUMP_SAMPLES_4BIT : XENG_MAX_DUMP_SAMPLES_8BIT;
-        s.wave = wave_path(s.cfg);
-        s.wt = choose_wt(s.cfg.n_inputs);
-        s.bt = 32 * s.wt;
+        set_choice(s, true, choose_wt(s.cfg.n_inputs));
         const int nb = (s.cfg.n_inputs + s.bt - 1) / s.bt;
         s.n_tiles = nb * (nb + 1) / 2;
         const size_t bytes = (size_t)s.tri * (size_t)s.cfg.n_chans * 8;
@@ -400,38 +513,12 @@ int xeng_create(const xeng_subarray *subs, int n_subs, void *hip_stream, xeng_ct
             return fail(XENG_ENOMEM, "hipMalloc(%zu) for subarray %d: %s", bytes, k,
                         hipGetErrorString(e));
         }
-        if (s.wave) wave_subs.push_back(k);
     }
-    // per (engine, input width): one launch group for all its wave-path
-    // subarrays when each fits one segment; otherwise one group per subarray
-    const int kinds[3][2] = {{XENG_ENGINE_I8, 4}, {XENG_ENGINE_I8, 8}, {XENG_ENGINE_FP8, 4}};
-    for (const auto &kd : kinds) {
-        std::vector<int> es;
-        bool one_group = true;
-        for (int k : wave_subs)
-            if (ctx->subs[k].cfg.engine == kd[0] && ctx->subs[k].cfg.in_bits == kd[1]) {
-                es.push_back(k);
-                if (ctx->subs[k].cfg.n_time > xeng::SEG_T) one_group = false;
-            }
-        if (es.empty()) continue;
-        std::vector<std::vector<int>> groups;
-        if (one_group) groups.push_back(es);
-        else
-            for (int k : es) groups.push_back({k});
-        for (auto &g : groups) {
-            ctx->plans.emplace_back();
-            ctx->plans.back().engine = kd[0];
-            ctx->plans.back().in_bits = kd[1];
-            ctx->plans.back().subs = g;
-        }
-    }
-    for (WavePlan &p : ctx->plans) {
-        build_schedule(p, ctx->subs, ctx->n_cu);
-        int rc = upload_plan(p);
-        if (rc) {
-            free_ctx(ctx);
-            return rc;
-        }
+    apply_tuning_cache(ctx);
+    int rc = replan(ctx);
+    if (rc) {
+        free_ctx(ctx);
+        return rc;
     }
     *out = ctx;
     return XENG_OK;
@@ -577,7 +664,10 @@ int xeng_plan_describe(const xeng_ctx *ctx, char *buf, size_t len)
                      (long long)s.n_tiles * s.cfg.n_chans, (long long)segs);
         js += item;
     }
-    js += "], \"persistent_launch_groups\": [";
+    js += "], \"tuned\": " + std::string(ctx->tuned ? "true" : "false") +
+          ", \"workgroups_per_cu\": " + std::to_string(ctx->wg_per_cu) +
+          ", \"schedule_order\": \"" + (ctx->order ? "costliest_first" : "locality") + "\"";
+    js += ", \"persistent_launch_groups\": [";
     for (size_t q = 0; q < ctx->plans.size(); ++q) {
         const WavePlan &p = ctx->plans[q];
         char item[256];
@@ -594,3 +684,6 @@ int xeng_plan_describe(const xeng_ctx *ctx, char *buf, size_t len)
 }
 
 } // extern "C"
+
+#include "xeng_stream.h"
+#include "xeng_tune.h"

@@ -1,0 +1,237 @@
+// Autotuner and whole-step graph capture. Part of the libxeng.so translation
+// unit (included by xeng.hip after the context API).
+//
+// The autotuner times, on the caller's own sample buffers, every kernel
+// family that can run each subarray (the persistent 128 x 128 tile kernel,
+// and the register-staging kernel with 32, 64 or 128-input tiles), keeps the
+// fastest per subarray, then times the schedule options of the batched
+// persistent launch (workgroups per CU, tile order) with all subarrays
+// together. Choices go to a process-wide cache keyed by the subarray shapes,
+// which xeng_create consults.
+#pragma once
+
+namespace {
+
+struct EvPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EvPair()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+// Mean milliseconds of `reps` runs of fn (after one untimed run); every run
+// starts from a logically zero accumulator, like a step after a dump.
+template <class Fn>
+int time_runs(xeng_ctx *ctx, int reps, Fn fn, float &ms)
+{
+    EvPair e;
+    HIP_TRY(hipEventCreate(&e.a));
+    HIP_TRY(hipEventCreate(&e.b));
+    auto zero_state = [&]() {
+        for (Sub &s : ctx->subs) s.acc_zero = true;
+    };
+    zero_state();
+    int rc = fn();
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(e.a, ctx->stream));
+    for (int r = 0; r < reps; ++r) {
+        zero_state();
+        rc = fn();
+        if (rc) return rc;
+    }
+    HIP_TRY(hipEventRecord(e.b, ctx->stream));
+    HIP_TRY(hipEventSynchronize(e.b));
+    HIP_TRY(hipEventElapsedTime(&ms, e.a, e.b));
+    ms /= (float)reps;
+    return XENG_OK;
+}
+
+// Milliseconds of one subarray's work alone under its current choice.
+int time_one(xeng_ctx *ctx, int k, const void *const *d_samples, int reps, float &ms)
+{
+    Sub &s = ctx->subs[k];
+    if (!s.wave)
+        return time_runs(ctx, reps, [&]() { return launch_regs(s, d_samples[k], ctx->stream); }, ms);
+    WavePlan p;
+    p.engine = s.cfg.engine;
+    p.in_bits = s.cfg.in_bits;
+    p.subs = {k};
+    build_schedule(p, ctx->subs, ctx->n_cu, ctx->wg_per_cu, ctx->order);
+    int rc = upload_plan(p);
+    if (!rc) rc = time_runs(ctx, reps, [&]() { return launch_wave(ctx, p, d_samples); }, ms);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (p.d_items) (void)hipFree(p.d_items);
+    if (p.d_wg_begin) (void)hipFree(p.d_wg_begin);
+    return rc;
+}
+
+int launch_all(xeng_ctx *ctx, const void *const *d_samples)
+{
+    for (WavePlan &p : ctx->plans) {
+        int rc = launch_wave(ctx, p, d_samples);
+        if (rc) return rc;
+    }
+    for (size_t k = 0; k < ctx->subs.size(); ++k)
+        if (!ctx->subs[k].wave) {
+            int rc = launch_regs(ctx->subs[k], d_samples[k], ctx->stream);
+            if (rc) return rc;
+        }
+    return XENG_OK;
+}
+
+} // namespace
+
+struct xeng_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+int xeng_autotune(xeng_ctx *ctx, const void *const *d_samples, int reps)
+{
+    if (!ctx || !d_samples) return fail(XENG_EINVAL, "NULL argument");
+    for (size_t k = 0; k < ctx->subs.size(); ++k) {
+        if (!d_samples[k]) return fail(XENG_EINVAL, "d_samples[%zu] is NULL", k);
+        if (((uintptr_t)d_samples[k] & 15) != 0)
+            return fail(XENG_EINVAL, "d_samples[%zu] is not 16-byte aligned", k);
+    }
+    if (reps < 1) reps = 1;
+    if (reps > 100) reps = 100;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    // (1) kernel family per subarray, each timed alone
+    for (size_t k = 0; k < ctx->subs.size(); ++k) {
+        Sub &s = ctx->subs[k];
+        if (s.cfg.engine == XENG_ENGINE_FP8) continue; // one kernel family only
+        struct Cand {
+            bool wave;
+            int wt;
+        };
+        std::vector<Cand> cands;
+        if (wave_path(s.cfg)) cands.push_back({true, 4});
+        const int N = s.cfg.n_inputs;
+        if (N <= 128) cands.push_back({false, 1});
+        if (N <= 1024) cands.push_back({false, 2});
+        cands.push_back({false, 4});
+        float best = 0.f;
+        Cand pick = cands[0];
+        for (size_t q = 0; q < cands.size(); ++q) {
+            set_choice(s, cands[q].wave, cands[q].wt);
+            float ms = 0.f;
+            int rc = time_one(ctx, (int)k, d_samples, reps, ms);
+            if (rc) return rc;
+            if (q == 0 || ms < best) {
+                best = ms;
+                pick = cands[q];
+            }
+        }
+        set_choice(s, pick.wave, pick.wt);
+    }
+    // (2) schedule of the batched persistent launch, all subarrays together
+    const int opts[4][2] = {{2, 0}, {2, 1}, {1, 0}, {1, 1}};
+    float best = 0.f;
+    int bw = 2, bo = 0;
+    bool any_wave = false;
+    for (const Sub &s : ctx->subs) any_wave |= s.wave;
+    for (int q = 0; q < (any_wave ? 4 : 1); ++q) {
+        ctx->wg_per_cu = opts[q][0];
+        ctx->order = opts[q][1];
+        int rc = replan(ctx);
+        if (rc) return rc;
+        float ms = 0.f;
+        rc = time_runs(ctx, reps, [&]() { return launch_all(ctx, d_samples); }, ms);
+        if (rc) return rc;
+        if (q == 0 || ms < best) {
+            best = ms;
+            bw = opts[q][0];
+            bo = opts[q][1];
+        }
+    }
+    ctx->wg_per_cu = bw;
+    ctx->order = bo;
+    int rc = replan(ctx);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    for (Sub &s : ctx->subs) {
+        s.acc_zero = true;
+        s.since_dump = 0;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const Sub &s : ctx->subs) g_tune_sub[key_of(s.cfg)] = SubChoice{s.wave, s.wt};
+        g_tune_sched[keys_of(ctx)] = SchedChoice{bw, bo};
+    }
+    ctx->tuned = true;
+    return XENG_OK;
+}
+
+int xeng_graph_create(xeng_ctx *ctx, const void *const *d_samples, void *const *out,
+                      xeng_graph **out_graph)
+{
+    if (!out_graph) return fail(XENG_EINVAL, "out_graph is NULL");
+    *out_graph = nullptr;
+    if (!ctx || !d_samples || !out) return fail(XENG_EINVAL, "NULL argument");
+    for (const Sub &s : ctx->subs)
+        if (s.since_dump != 0)
+            return fail(XENG_EINVAL, "graph capture needs a context with nothing accumulated");
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    hipStream_t cap = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipStream_t saved = ctx->stream;
+    ctx->stream = cap;
+    hipGraph_t g = nullptr;
+    int rc = XENG_OK;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        rc = fail(XENG_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    } else {
+        rc = xeng_correlate(ctx, d_samples);
+        if (!rc) rc = xeng_dump(ctx, out, 1, 1);
+        e = hipStreamEndCapture(cap, &g);
+        if (!rc && e != hipSuccess) rc = fail(XENG_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    }
+    ctx->stream = saved;
+    for (Sub &s : ctx->subs) {
+        s.acc_zero = true;
+        s.since_dump = 0;
+    }
+    (void)hipStreamDestroy(cap);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    xeng_graph *xg = new (std::nothrow) xeng_graph;
+    if (!xg) {
+        (void)hipGraphDestroy(g);
+        return fail(XENG_ENOMEM, "host allocation failed");
+    }
+    xg->graph = g;
+    e = hipGraphInstantiate(&xg->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        delete xg;
+        return fail(XENG_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    *out_graph = xg;
+    return XENG_OK;
+}
+
+int xeng_graph_launch(xeng_graph *g, void *hip_stream)
+{
+    if (!g) return fail(XENG_EINVAL, "graph is NULL");
+    HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)hip_stream));
+    return XENG_OK;
+}
+
+int xeng_graph_destroy(xeng_graph *g)
+{
+    if (!g) return XENG_OK;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return XENG_OK;
+}
+
+} // extern "C"

@@ -23,6 +23,9 @@ EXPORTS = (
     "xeng_create", "xeng_correlate", "xeng_dump", "xeng_destroy", "xeng_set_stream",
     "xeng_samples_since_dump", "xeng_max_dump_samples", "xeng_plan_describe",
     "xeng_strerror", "xeng_last_error",
+    "xeng_stream_create", "xeng_stream_next_slot", "xeng_stream_push", "xeng_stream_dump_wait",
+    "xeng_stream_gulp_times", "xeng_stream_gulps", "xeng_stream_destroy",
+    "xeng_autotune", "xeng_graph_create", "xeng_graph_launch", "xeng_graph_destroy",
 )
 
 
@@ -72,6 +75,30 @@ def load():
     lib.xeng_strerror.restype = ctypes.c_char_p
     lib.xeng_last_error.argtypes = []
     lib.xeng_last_error.restype = ctypes.c_char_p
+    lib.xeng_stream_create.argtypes = [ctypes.POINTER(Subarray), i32, i32, pp, i32,
+                                       ctypes.POINTER(vp)]
+    lib.xeng_stream_create.restype = i32
+    lib.xeng_stream_next_slot.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    lib.xeng_stream_next_slot.restype = i32
+    lib.xeng_stream_push.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.xeng_stream_push.restype = i32
+    lib.xeng_stream_dump_wait.argtypes = [vp, i64, ctypes.POINTER(vp)]
+    lib.xeng_stream_dump_wait.restype = i32
+    lib.xeng_stream_gulp_times.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_float),
+                                           ctypes.POINTER(ctypes.c_float)]
+    lib.xeng_stream_gulp_times.restype = i32
+    lib.xeng_stream_gulps.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.xeng_stream_gulps.restype = i32
+    lib.xeng_stream_destroy.argtypes = [vp]
+    lib.xeng_stream_destroy.restype = i32
+    lib.xeng_autotune.argtypes = [vp, pp, i32]
+    lib.xeng_autotune.restype = i32
+    lib.xeng_graph_create.argtypes = [vp, pp, pp, ctypes.POINTER(vp)]
+    lib.xeng_graph_create.restype = i32
+    lib.xeng_graph_launch.argtypes = [vp, vp]
+    lib.xeng_graph_launch.restype = i32
+    lib.xeng_graph_destroy.argtypes = [vp]
+    lib.xeng_graph_destroy.restype = i32
     _lib = lib
     return lib
 
@@ -135,8 +162,7 @@ class Correlator:
     def set_stream(self, stream):
         _check(self._lib.xeng_set_stream(self._ctx, ctypes.c_void_p(_stream_handle(stream))))
 
-    def correlate(self, samples):
-        """samples: one device tensor (or device pointer int) per subarray."""
+    def _sample_ptrs(self, samples):
         if not isinstance(samples, (list, tuple)):
             samples = [samples]
         if len(samples) != len(self.subs):
@@ -146,14 +172,36 @@ class Correlator:
             if isinstance(x, int):
                 ptrs.append(x)
                 continue
-            s = self.subs[k]
             want = self.sample_shape(k)
             if tuple(x.shape) != want:
                 raise ValueError("subarray %d: samples shape %s, expected %s" % (k, tuple(x.shape), want))
             if not x.is_cuda or not x.is_contiguous() or x.element_size() != 1:
                 raise ValueError("subarray %d: samples must be a contiguous 1-byte device tensor" % k)
             ptrs.append(x.data_ptr())
-        _check(self._lib.xeng_correlate(self._ctx, _ptrs(ptrs)))
+        return _ptrs(ptrs)
+
+    def correlate(self, samples):
+        """samples: one device tensor (or device pointer int) per subarray."""
+        _check(self._lib.xeng_correlate(self._ctx, self._sample_ptrs(samples)))
+
+    def autotune(self, samples, reps: int = 5):
+        """Time the kernel and schedule choices on these samples and keep the fastest."""
+        _check(self._lib.xeng_autotune(self._ctx, self._sample_ptrs(samples), int(reps)))
+
+    def capture(self, samples, out):
+        """Capture correlate(samples) + dump(out, device, reset) as a replayable Graph."""
+        import torch
+        if not isinstance(out, (list, tuple)):
+            out = [out]
+        for k, o in enumerate(out):
+            if tuple(o.shape) != self.vis_shape(k) or o.dtype != torch.int32 or not o.is_cuda \
+                    or not o.is_contiguous():
+                raise ValueError("subarray %d: output must be a contiguous device int32 %s"
+                                 % (k, self.vis_shape(k)))
+        g = ctypes.c_void_p()
+        _check(self._lib.xeng_graph_create(self._ctx, self._sample_ptrs(samples),
+                                           _ptrs([o.data_ptr() for o in out]), ctypes.byref(g)))
+        return Graph(self._lib, g, self)
 
     def dump(self, out=None, reset: bool = True, device: bool = True):
         """Copy the sums into out (allocated if None); returns the list of outputs."""
@@ -197,6 +245,104 @@ class Correlator:
         if getattr(self, "_ctx", None) and self._ctx.value:
             rc = self._lib.xeng_destroy(self._ctx)
             self._ctx = ctypes.c_void_p()
+            _check(rc)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Stream:
+    """Streaming integration of one subarray through a device ring of gulps.
+
+    ``host_dumps``: optional list of host int32 tensors ``[F][tri(N)][2]``
+    (pinned) that receive dump d in ``host_dumps[d % len]``.
+    """
+
+    def __init__(self, subarray, n_slots: int = 4, dump_every: int = 26, host_dumps=None):
+        s = subarray if isinstance(subarray, Subarray) else Subarray(
+            int(subarray["n_inputs"]), int(subarray["n_chans"]), int(subarray["n_time"]),
+            int(subarray.get("in_bits", 4)), int(subarray.get("engine", ENGINE_I8)))
+        self.sub = s
+        self._lib = load()
+        self._host = list(host_dumps) if host_dumps else []
+        shape = (s.n_chans, tri(s.n_inputs), 2)
+        for h in self._host:
+            if tuple(h.shape) != shape or h.is_cuda or not h.is_contiguous():
+                raise ValueError("host dump buffers must be contiguous host int32 %s" % (shape,))
+        self._s = ctypes.c_void_p()
+        hp = _ptrs([h.data_ptr() for h in self._host]) if self._host else None
+        _check(self._lib.xeng_stream_create(ctypes.byref(s), n_slots, dump_every, hp,
+                                            len(self._host), ctypes.byref(self._s)))
+
+    def next_slot(self):
+        """(device pointer of the next gulp's slot, ingest hipStream_t handle)."""
+        p, st = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(self._lib.xeng_stream_next_slot(self._s, ctypes.byref(p), ctypes.byref(st)))
+        return p.value, st.value
+
+    def push(self) -> int:
+        g = ctypes.c_int64()
+        _check(self._lib.xeng_stream_push(self._s, ctypes.byref(g)))
+        return g.value
+
+    def dump_wait(self, d: int) -> int:
+        """Wait for dump d; returns the device pointer of its dump buffer."""
+        p = ctypes.c_void_p()
+        _check(self._lib.xeng_stream_dump_wait(self._s, d, ctypes.byref(p)))
+        return p.value
+
+    def gulp_times(self, g: int):
+        """(arrival -> done ms, filled -> done ms) of gulp g."""
+        a, r = ctypes.c_float(), ctypes.c_float()
+        _check(self._lib.xeng_stream_gulp_times(self._s, g, ctypes.byref(a), ctypes.byref(r)))
+        return a.value, r.value
+
+    def gulps(self) -> int:
+        v = ctypes.c_int64()
+        _check(self._lib.xeng_stream_gulps(self._s, ctypes.byref(v)))
+        return v.value
+
+    def close(self):
+        if getattr(self, "_s", None) and self._s.value:
+            rc = self._lib.xeng_stream_destroy(self._s)
+            self._s = ctypes.c_void_p()
+            _check(rc)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A captured step (correlate + dump + reset) of a Correlator."""
+
+    def __init__(self, lib, handle, owner):
+        self._lib, self._g, self._owner = lib, handle, owner
+
+    def launch(self, stream=None):
+        _check(self._lib.xeng_graph_launch(self._g, ctypes.c_void_p(_stream_handle(stream))))
+
+    def close(self):
+        if getattr(self, "_g", None) and self._g.value:
+            rc = self._lib.xeng_graph_destroy(self._g)
+            self._g = ctypes.c_void_p()
             _check(rc)
 
     def __enter__(self):

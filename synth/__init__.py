@@ -6,6 +6,7 @@ arithmetic, so both the CPU oracle's tests and the GPU path can take their
 inputs from it without sharing any of the method.
 """
 from .gen import (  # noqa: F401
+    BATCH_SHAPES,
     SEED_BASE,
     TONE_AMP,
     TONE_NU,

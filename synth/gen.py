@@ -163,7 +163,11 @@ WORKLOADS = {
     "leda_gulp": dict(n_inputs=512, n_chans=128, n_time=8192, sigma=2.5, in_bits=4, tone=True, k=1),
     "fp8_variant": dict(n_inputs=512, n_chans=256, n_time=16384, sigma=2.5, in_bits=4, tone=False, k=2),
     "int8_variant": dict(n_inputs=512, n_chans=256, n_time=16384, sigma=20.0, in_bits=8, tone=False, k=2),
+    # subarray s of the batch takes (n_inputs, n_chans) = BATCH_SHAPES[s]
+    "batch": dict(n_inputs=None, n_chans=None, n_time=4096, sigma=2.5, in_bits=4, tone=False, k=3),
 }
+# Batched subarrays of uneven size: (N, F) with equal input bytes per call for N >= 256.
+BATCH_SHAPES = [(64, 512), (256, 256), (512, 128), (1024, 64), (2048, 32)]
 
 
 def fixed_tone(n_chans: int, amp: float = TONE_AMP, nu: float = TONE_NU, phi0: float = 0.0):
@@ -183,6 +187,8 @@ def workload(name: str, subarray: int = 0, n_time: int | None = None,
     and ``im`` are the int8 components when ``components`` is true, else None.
     """
     w = dict(WORKLOADS[name])
+    if name == "batch":
+        w["n_inputs"], w["n_chans"] = BATCH_SHAPES[subarray]
     T = n_time or w["n_time"]
     F = n_chans or w["n_chans"]
     N = n_inputs or w["n_inputs"]

@@ -1,0 +1,128 @@
+"""Batched subarrays of uneven N: autotuned kernel choices, one persistent
+launch per engine and input width, and whole-step HIP-graph replays, all
+bit-exact against the oracle."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def rand4(rng, T, F, N):
+    re = rng.integers(-8, 8, size=(T, F, N)).astype(np.int8)
+    im = rng.integers(-8, 8, size=(T, F, N)).astype(np.int8)
+    return synth.pack4(re, im)
+
+
+SMALL = [(64, 8, 512), (128, 4, 300), (40, 3, 200), (96, 2, 130)]  # (N, F, T)
+
+
+def test_graph_replays_match_oracle(torch_cuda, oracle_lib):
+    # replays read refilled buffers; eager work and syncs between replays
+    from paper_1411_3751_amd import Correlator
+    torch = torch_cuda
+    print("case graph replays", flush=True)
+    rng = np.random.default_rng(31)
+    subs = [dict(n_inputs=N, n_chans=F, n_time=T) for (N, F, T) in SMALL]
+    dev = [torch.empty((T, F, N), dtype=torch.uint8, device="cuda") for (N, F, T) in SMALL]
+    out = [torch.empty((F, N * (N + 1) // 2, 2), dtype=torch.int32, device="cuda")
+           for (N, F, T) in SMALL]
+    with Correlator(subs) as c:
+        with c.capture(dev, out) as g:
+            for rep in range(3):
+                host = [rand4(rng, T, F, N) for (N, F, T) in SMALL]
+                for d, h in zip(dev, host):
+                    d.copy_(torch.from_numpy(h))
+                torch.cuda.synchronize()
+                g.launch()
+                torch.cuda.synchronize()
+                for (N, F, T), h, o in zip(SMALL, host, out):
+                    want = oracle_lib.narrow(oracle_lib.correlate(h, 4))
+                    assert np.array_equal(o.cpu().numpy(), want), (rep, N)
+        # the context is left reset: an eager step after the graph starts from zero
+        h = [rand4(rng, T, F, N) for (N, F, T) in SMALL]
+        c.correlate([torch.from_numpy(x).cuda() for x in h])
+        for (N, F, T), x, o in zip(SMALL, h, c.dump()):
+            assert np.array_equal(o.cpu().numpy(), oracle_lib.narrow(oracle_lib.correlate(x, 4)))
+
+
+def test_graph_needs_reset_context(torch_cuda):
+    from paper_1411_3751_amd import Correlator, XengError
+    from paper_1411_3751_amd.xeng import XENG_EINVAL
+    torch = torch_cuda
+    x = torch.zeros((64, 2, 16), dtype=torch.uint8, device="cuda")
+    o = torch.empty((2, 136, 2), dtype=torch.int32, device="cuda")
+    with Correlator([dict(n_inputs=16, n_chans=2, n_time=64)]) as c:
+        c.correlate([x])
+        with pytest.raises(XengError) as ei:
+            c.capture([x], [o])
+        assert ei.value.code == XENG_EINVAL
+
+
+def test_autotune_choices_stay_exact_and_are_cached(torch_cuda, oracle_lib):
+    from paper_1411_3751_amd import Correlator
+    torch = torch_cuda
+    print("case autotune", flush=True)
+    rng = np.random.default_rng(32)
+    shapes = [(64, 16, 1024), (48, 4, 700), (256, 3, 500)]
+    subs = [dict(n_inputs=N, n_chans=F, n_time=T) for (N, F, T) in shapes]
+    host = [rand4(rng, T, F, N) for (N, F, T) in shapes]
+    dev = [torch.from_numpy(h).cuda() for h in host]
+    with Correlator(subs) as c:
+        c.correlate(dev)
+        c.autotune(dev, reps=2)   # discards the sums above
+        assert c.samples_since_dump() == 0
+        plan = c.plan()
+        assert plan["tuned"] is True
+        c.correlate(dev)
+        c.correlate(dev)
+        outs = [o.cpu().numpy() for o in c.dump()]
+    for (N, F, T), h, o in zip(shapes, host, outs):
+        assert np.array_equal(o, oracle_lib.narrow(oracle_lib.correlate(h, 4) * 2)), N
+    with Correlator(subs) as c2:
+        assert c2.plan()["tuned"] is True
+        assert [s["kernel"] for s in c2.plan()["subarrays"]] == \
+            [s["kernel"] for s in plan["subarrays"]]
+
+
+def test_batch_configuration_sampled(torch_cuda, oracle_lib):
+    # the five-subarray batch (N = 64 ... 2048, 4096 samples): autotuned,
+    # captured, replayed twice; sampled channels of every subarray checked
+    from paper_1411_3751_amd import Correlator
+    torch = torch_cuda
+    print("case batch configuration", flush=True)
+    streams, subs = [], []
+    for s in range(len(synth.BATCH_SHAPES)):
+        x, _, _, meta = synth.workload("batch", subarray=s)
+        streams.append(x)
+        subs.append(dict(n_inputs=meta["n_inputs"], n_chans=meta["n_chans"], n_time=meta["n_time"]))
+    dev = [torch.from_numpy(x).cuda() for x in streams]
+    out = [torch.empty((d["n_chans"], d["n_inputs"] * (d["n_inputs"] + 1) // 2, 2),
+                       dtype=torch.int32, device="cuda") for d in subs]
+    rng = np.random.default_rng(33)
+    with Correlator(subs) as c:
+        c.autotune(dev, reps=2)
+        print("plan", c.plan(), flush=True)
+        with c.capture(dev, out) as g:
+            for _ in range(2):
+                g.launch()
+            torch.cuda.synchronize()
+    for x, d, o in zip(streams, subs, out):
+        N, F = d["n_inputs"], d["n_chans"]
+        got = o.cpu().numpy()
+        n_full = {64: F, 256: 8, 512: 4, 1024: 2, 2048: 1}[N]
+        chans = sorted(rng.choice(F, n_full, replace=False).tolist())
+        want = oracle_lib.narrow(oracle_lib.correlate(x, 4, chans=chans))
+        assert np.array_equal(got[chans], want), N
+        for f in rng.choice([f for f in range(F) if f not in chans] or [0], 3):
+            w = rng.integers(-4, 5, size=(N, 2)).astype(np.int64)
+            assert oracle_lib.projection_check(x, 4, int(f), got[f], w) == 0, (N, f)

@@ -1,0 +1,131 @@
+"""Streaming integration through the device gulp ring (xeng_stream_*), and the
+GPU side of the input generator.
+
+Gulps are produced on the device by the counter-based generator (a drifting
+common tone, phase-continuous across gulps), pushed through a 4-slot ring and
+dumped every few gulps; each dump must equal the oracle's sums over exactly
+the gulps of its period, regenerated on the host.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import synth.gpu
+    synth.gpu.build()
+    return torch
+
+
+def drift_tone(F, gulp):
+    return (synth.TONE_AMP, lambda t: synth.drift_phase(t, gulp), synth.tone_channels(F))
+
+
+@pytest.mark.parametrize("in_bits,N", [(4, 48), (8, 40), (4, 37)])
+def test_gpu_generator_matches_host(torch_cuda, in_bits, N):
+    import synth.gpu
+    torch = torch_cuda
+    print("case generator in_bits=%d N=%d" % (in_bits, N), flush=True)
+    T, F, t0, seed = 300, 16, 5000, 4242
+    sigma = 2.5 if in_bits == 4 else 20.0
+    tone = drift_tone(F, 128)
+    gen = synth.gpu.DeviceStream(seed, F, N, in_bits, sigma, tone=tone, t_total=t0 + T)
+    shape = (T, F, N) if in_bits == 4 else (T, F, N, 2)
+    buf = torch.empty(shape, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream()
+    gen.fill(buf.data_ptr(), t0, T, s.cuda_stream)
+    torch.cuda.synchronize()
+    want, _, _ = synth.stream(seed, T, F, N, in_bits, sigma, t0=t0, tone=tone)
+    got = buf.cpu().numpy()
+    if in_bits == 8:
+        got = got.view(np.int8)
+    assert np.array_equal(got, want)
+
+
+def run_stream(torch, N, F, T, n_gulps, dump_every, in_bits=4, host=True):
+    import synth.gpu
+    from paper_1411_3751_amd import Stream
+    seed = 99
+    sigma = 2.5 if in_bits == 4 else 20.0
+    tone = drift_tone(F, T)
+    gen = synth.gpu.DeviceStream(seed, F, N, in_bits, sigma, tone=tone, t_total=n_gulps * T)
+    shape = (F, N * (N + 1) // 2, 2)
+    hd = [torch.empty(shape, dtype=torch.int32, pin_memory=True) for _ in range(2)] if host else None
+    sub = dict(n_inputs=N, n_chans=F, n_time=T, in_bits=in_bits)
+    dumps, times = [], []
+    with Stream(sub, n_slots=4, dump_every=dump_every, host_dumps=hd) as st:
+        for g in range(n_gulps):
+            ptr, ist = st.next_slot()
+            gen.fill(ptr, g * T, T, ist)
+            st.push()
+            if (g + 1) % dump_every == 0:
+                d = (g + 1) // dump_every - 1
+                dp = st.dump_wait(d)
+                if host:
+                    dumps.append(hd[d % 2].numpy().copy())
+                else:
+                    h = np.empty(shape, np.int32)
+                    hip = ctypes.CDLL("libamdhip64.so")
+                    assert hip.hipMemcpy(ctypes.c_void_p(h.ctypes.data), ctypes.c_void_p(dp),
+                                         ctypes.c_size_t(h.nbytes), 2) == 0
+                    dumps.append(h)
+        for g in range(n_gulps):
+            times.append(st.gulp_times(g))
+        assert st.gulps() == n_gulps
+    return dumps, times, seed, sigma, tone
+
+
+@pytest.mark.parametrize("host", [True, False])
+def test_stream_dumps_match_oracle(torch_cuda, oracle_lib, host):
+    print("case stream host=%s" % host, flush=True)
+    N, F, T, dump_every, n_gulps = 128, 16, 2048, 3, 7
+    dumps, times, seed, sigma, tone = run_stream(torch_cuda, N, F, T, n_gulps, dump_every,
+                                                 host=host)
+    assert len(dumps) == 2
+    for d, got in enumerate(dumps):
+        x, _, _ = synth.stream(seed, dump_every * T, F, N, 4, sigma, t0=d * dump_every * T,
+                               tone=tone)
+        want = oracle_lib.narrow(oracle_lib.correlate(x, 4))
+        bad = np.argwhere(got != want)
+        assert bad.size == 0, "dump %d first mismatches %s" % (d, bad[:5].tolist())
+    for a, r in times:
+        assert a >= r > 0
+
+
+def test_stream_8bit_and_odd_n(torch_cuda, oracle_lib):
+    # 8-bit gulps with N not a multiple of 8 take the register-staging kernel
+    print("case stream 8-bit N=30", flush=True)
+    N, F, T, dump_every, n_gulps = 30, 8, 1000, 2, 4
+    dumps, _, seed, sigma, tone = run_stream(torch_cuda, N, F, T, n_gulps, dump_every, in_bits=8)
+    for d, got in enumerate(dumps):
+        x, _, _ = synth.stream(seed, dump_every * T, F, N, 8, sigma, t0=d * dump_every * T,
+                               tone=tone)
+        assert np.array_equal(got, oracle_lib.narrow(oracle_lib.correlate(x, 8)))
+
+
+def test_stream_errors(torch_cuda):
+    from paper_1411_3751_amd import Stream, XengError
+    from paper_1411_3751_amd.xeng import XENG_EINVAL, XENG_ERANGE
+    sub = dict(n_inputs=16, n_chans=2, n_time=64)
+    with pytest.raises(XengError) as ei:
+        Stream(sub, n_slots=1)
+    assert ei.value.code == XENG_EINVAL
+    with pytest.raises(XengError) as ei:
+        Stream(dict(n_inputs=16, n_chans=2, n_time=40000, in_bits=8), n_slots=2, dump_every=2)
+    assert ei.value.code == XENG_ERANGE
+    with Stream(sub, n_slots=2, dump_every=2) as st:
+        with pytest.raises(XengError) as ei:
+            st.push()
+        assert ei.value.code == XENG_EINVAL
+        with pytest.raises(XengError) as ei:
+            st.dump_wait(0)
+        assert ei.value.code == XENG_EINVAL
