@@ -130,6 +130,28 @@ int xeng_max_dump_samples(const xeng_ctx *ctx, int sub, int64_t *out);
 int xeng_plan_describe(const xeng_ctx *ctx, char *buf, size_t len);
 
 /*
+ * ---- Fast-cadence autocorrelations (Section 2.6: total power of chosen
+ * inputs, e.g. outrigger antennas, integrated and dumped more often than
+ * the cross power, by selective dumping and zeroing of accumulator cells).
+ *
+ * Select the inputs of subarray sub (host array of n indices in [0, N);
+ * n = 0 clears the selection). Allocates a small device list; synchronises
+ * the context stream. Errors: XENG_EINVAL, XENG_ENOMEM, XENG_EHIP.
+ */
+int xeng_set_fast_autos(xeng_ctx *ctx, int sub, const int32_t *inputs, int n);
+
+/*
+ * For every subarray with a selection, write Re V_ii of the selected inputs
+ * to out[s] (device int32 [n_chans][n], in selection order; Im V_ii is
+ * identically 0) and, if reset != 0, zero those cells so that they integrate
+ * afresh. Every other cell (the cross power, unselected autocorrelations)
+ * keeps integrating to the main dump, and the main dump reports the
+ * selected autocorrelations since their last fast reset. out may be NULL
+ * when reset != 0. Enqueued on the context stream. out_is_device must be 1.
+ */
+int xeng_dump_fast_autos(xeng_ctx *ctx, void *const *out, int out_is_device, int reset);
+
+/*
  * ---- Autotuning and graph capture (batched subarrays of uneven N in one
  * persistent launch per engine and input width).
  *

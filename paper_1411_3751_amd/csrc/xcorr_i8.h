@@ -323,6 +323,30 @@ __global__ void fill_zero_kernel(int4 *p, size_t n16, int32_t *tail, size_t ntai
 }
 
 
+// Fast-cadence autocorrelations (Section 2.6: the autocorrelations of chosen
+// inputs are dumped and zeroed more often than the cross power, by selective
+// dumping and zeroing of accumulator cells). out[f][q] = Re V_ii of input
+// i = inputs[q] in channel f (Im V_ii is identically 0); reset clears only
+// that Re word: the diagonal's Im word holds -S_i, which the dump of every
+// cross cell of row i needs for the whole integration. One thread per
+// (channel, selected input), grid-stride.
+__global__ __launch_bounds__(256) void fast_autos_kernel(uint2 *__restrict__ acc, int64_t tri,
+                                                         int32_t n_chans,
+                                                         const int32_t *__restrict__ inputs,
+                                                         int32_t n, int32_t *__restrict__ out,
+                                                         int32_t reset, int32_t acc_zero)
+{
+    const int64_t total = (int64_t)n_chans * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t f = e / n;
+        const int64_t i = inputs[e - f * n];
+        const int64_t c = f * tri + i * (i + 1) / 2 + i;
+        if (out) out[e] = acc_zero ? 0 : (int32_t)acc[c].x;
+        if (reset && !acc_zero) acc[c].x = 0u;
+    }
+}
+
 // Dump of a raw accumulator into the output convention: Re unchanged,
 // Im V_ij = raw_ij - raw_ii (the diagonal entry of row i holds -S_i).
 // Arithmetic is modulo 2^32; the true value fits int32.

@@ -25,8 +25,7 @@
 // Each wave computes a 64 x 64 quarter of the tile as 2 x 2 MFMA tiles of
 // 32 x 32. On a diagonal tile (J = I, only the I half is copied) three
 // quarters are needed: waves 0, 1 take the diagonal ones, wave 2 the lower
-// one, and wave 3 repeats wave 2's work without writing it (every wave runs
-// the same branch-free stage loop).
+// one, and wave 3 only copies and synchronises.
 //
 // Operands: re, im and ~im (= -im - 1, so that -(-8) or -(-128) never has to
 // fit in int8); 4-bit values are scaled by 16 by the nibble masks (see
@@ -398,7 +397,7 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
     // ip, its J inputs at jp of the staged row (J half at 128), output origin
     // (r0, c0). On a diagonal tile the J half is not copied (J = I): waves 0,
     // 1 take the diagonal quarters, wave 2 the lower off-diagonal quarter,
-    // and wave 3 repeats wave 2's work without writing it.
+    // and wave 3 has none (write = false: it computes and writes nothing).
     auto role = [&](const WgItem &w, int &ip, int &jp, int &r0, int &c0, bool &write) {
         const int bi = (int)(w.ij & 0xFFFFu), bj = (int)(w.ij >> 16);
         const int I0 = 128 * bi, J0 = 128 * bj;
@@ -529,16 +528,22 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
         // and multiply, then publish and read the next stage
         for (int k = 0; k < nst; ++k, ++s) {
             if (issued < n_total) d_issue();
-            if constexpr (ENG == ENG_F8) {
-                wg_f8_stage(RA, accR, accI);
-            } else if constexpr (IN_BITS == 4) {
-                wg_unpack(RA, 0, O0);
-                wg_mfma(O0, accR, accI);
-                wg_unpack(RA, 1, O0);
-                wg_mfma(O0, accR, accI);
-            } else {
-                wg8_unpack(RA, O0);
-                wg_mfma(O0, accR, accI);
+            // wave 3 of a diagonal tile has no quarter of its own: it keeps
+            // copying and synchronising but leaves its SIMD's matrix core to
+            // the other workgroup (one uniform branch per stage, outside the
+            // MFMA chain)
+            if (write) {
+                if constexpr (ENG == ENG_F8) {
+                    wg_f8_stage(RA, accR, accI);
+                } else if constexpr (IN_BITS == 4) {
+                    wg_unpack(RA, 0, O0);
+                    wg_mfma(O0, accR, accI);
+                    wg_unpack(RA, 1, O0);
+                    wg_mfma(O0, accR, accI);
+                } else {
+                    wg8_unpack(RA, O0);
+                    wg_mfma(O0, accR, accI);
+                }
             }
             if (s + 1 < n_total) {
                 prep_stage(s + 1);

@@ -69,6 +69,8 @@ struct Sub {
     int wt = 4;                // register kernel: wave tile edge in 16-row sub-blocks
     int bt = 128;              // register kernel: workgroup tile edge
     int n_tiles = 0;           // register kernel: tiles per channel
+    int32_t *d_fast = nullptr; // inputs whose autocorrelations have a fast cadence
+    int n_fast = 0;
 };
 
 // One persistent-kernel launch group: the subarrays it covers and its schedule.
@@ -450,8 +452,10 @@ void apply_tuning_cache(xeng_ctx *ctx)
 
 void free_ctx(xeng_ctx *ctx)
 {
-    for (Sub &s : ctx->subs)
+    for (Sub &s : ctx->subs) {
         if (s.d_acc) (void)hipFree(s.d_acc);
+        if (s.d_fast) (void)hipFree(s.d_fast);
+    }
     free_plans(ctx);
     if (ctx->d_stage) (void)hipFree(ctx->d_stage);
     delete ctx;
@@ -474,6 +478,51 @@ const char *xeng_strerror(int code)
 }
 
 const char *xeng_last_error(void) { return g_last_error.c_str(); }
+
+int xeng_set_fast_autos(xeng_ctx *ctx, int sub, const int32_t *inputs, int n)
+{
+    if (!ctx) return fail(XENG_EINVAL, "ctx is NULL");
+    if (sub < 0 || sub >= (int)ctx->subs.size()) return fail(XENG_EINVAL, "sub %d out of range", sub);
+    if (n < 0 || (n > 0 && !inputs)) return fail(XENG_EINVAL, "bad input list");
+    Sub &s = ctx->subs[sub];
+    if (n > s.cfg.n_inputs) return fail(XENG_EINVAL, "%d inputs selected of %d", n, s.cfg.n_inputs);
+    for (int q = 0; q < n; ++q)
+        if (inputs[q] < 0 || inputs[q] >= s.cfg.n_inputs)
+            return fail(XENG_EINVAL, "input %d out of [0, %d)", inputs[q], s.cfg.n_inputs);
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (s.d_fast) (void)hipFree(s.d_fast);
+    s.d_fast = nullptr;
+    s.n_fast = 0;
+    if (n == 0) return XENG_OK;
+    hipError_t e = hipMalloc((void **)&s.d_fast, sizeof(int32_t) * (size_t)n);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(XENG_ENOMEM, "hipMalloc for the fast-cadence input list: %s", hipGetErrorString(e));
+    }
+    HIP_TRY(hipMemcpy(s.d_fast, inputs, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
+    s.n_fast = n;
+    return XENG_OK;
+}
+
+int xeng_dump_fast_autos(xeng_ctx *ctx, void *const *out, int out_is_device, int reset)
+{
+    if (!ctx) return fail(XENG_EINVAL, "ctx is NULL");
+    if (!out && !reset) return fail(XENG_EINVAL, "out is NULL and reset is 0");
+    if (out && !out_is_device) return fail(XENG_EINVAL, "fast-cadence dumps go to device memory");
+    for (size_t k = 0; k < ctx->subs.size(); ++k) {
+        Sub &s = ctx->subs[k];
+        if (s.n_fast == 0) continue;
+        if (out && !out[k]) return fail(XENG_EINVAL, "out[%zu] is NULL", k);
+        const int64_t total = (int64_t)s.cfg.n_chans * s.n_fast;
+        const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+        hipLaunchKernelGGL(xeng::fast_autos_kernel, dim3(blocks), dim3(256), 0, ctx->stream,
+                           (uint2 *)s.d_acc, s.tri, s.cfg.n_chans, s.d_fast, s.n_fast,
+                           out ? (int32_t *)out[k] : (int32_t *)nullptr, reset ? 1 : 0,
+                           s.acc_zero ? 1 : 0);
+        HIP_TRY(hipGetLastError());
+    }
+    return XENG_OK;
+}
 
 int xeng_create(const xeng_subarray *subs, int n_subs, void *hip_stream, xeng_ctx **out)
 {

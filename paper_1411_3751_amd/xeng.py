@@ -26,6 +26,7 @@ EXPORTS = (
     "xeng_stream_create", "xeng_stream_next_slot", "xeng_stream_push", "xeng_stream_dump_wait",
     "xeng_stream_gulp_times", "xeng_stream_gulps", "xeng_stream_destroy",
     "xeng_autotune", "xeng_graph_create", "xeng_graph_launch", "xeng_graph_destroy",
+    "xeng_set_fast_autos", "xeng_dump_fast_autos",
 )
 
 
@@ -91,6 +92,10 @@ def load():
     lib.xeng_stream_gulps.restype = i32
     lib.xeng_stream_destroy.argtypes = [vp]
     lib.xeng_stream_destroy.restype = i32
+    lib.xeng_set_fast_autos.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32), i32]
+    lib.xeng_set_fast_autos.restype = i32
+    lib.xeng_dump_fast_autos.argtypes = [vp, pp, i32, i32]
+    lib.xeng_dump_fast_autos.restype = i32
     lib.xeng_autotune.argtypes = [vp, pp, i32]
     lib.xeng_autotune.restype = i32
     lib.xeng_graph_create.argtypes = [vp, pp, pp, ctypes.POINTER(vp)]
@@ -225,6 +230,25 @@ class Correlator:
 
     def reset(self):
         _check(self._lib.xeng_dump(self._ctx, None, 1, 1))
+
+    def set_fast_autos(self, inputs, k: int = 0):
+        """Select inputs of subarray k whose autocorrelations get a fast cadence."""
+        arr = (ctypes.c_int32 * len(inputs))(*[int(i) for i in inputs])
+        _check(self._lib.xeng_set_fast_autos(self._ctx, k, arr, len(inputs)))
+        self._fast = getattr(self, "_fast", {})
+        self._fast[k] = len(inputs)
+
+    def dump_fast_autos(self, reset: bool = True):
+        """Re V_ii of the selected inputs, int32 device tensors [n_chans][n] per subarray
+        (None for subarrays without a selection)."""
+        import torch
+        fast = getattr(self, "_fast", {})
+        dev = torch.device("cuda", torch.cuda.current_device())
+        outs = [torch.empty((s.n_chans, fast[k]), dtype=torch.int32, device=dev)
+                if fast.get(k) else None for k, s in enumerate(self.subs)]
+        ptrs = _ptrs([o.data_ptr() if o is not None else 0 for o in outs])
+        _check(self._lib.xeng_dump_fast_autos(self._ctx, ptrs, 1, 1 if reset else 0))
+        return outs
 
     def samples_since_dump(self, k: int = 0) -> int:
         v = ctypes.c_int64()
