@@ -178,6 +178,29 @@ __device__ __forceinline__ void wg8_unpack(const WgRaw &R, WgOps &o)
     }
 }
 
+// The MFMAs of blocks [b0, b1) of one K step, blocks in the order
+// (x, y) = (0, 0), (1, 0), (0, 1), (1, 1):
+//   accR[x][y] += re_I re_J + im_I im_J,  accI[x][y] += re_I ~im_J + im_I re_J.
+template <int B0, int B1>
+__device__ __forceinline__ void wg_mfma_blocks(const WgOps &o, i32x16 (&accR)[2][2],
+                                               i32x16 (&accI)[2][2])
+{
+#pragma unroll
+    for (int b = B0; b < B1; ++b) {
+        const int x = b & 1, y = b >> 1;
+        accR[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.reI[x], o.reJ[y], accR[x][y], 0, 0, 0);
+        accI[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.reI[x], o.niJ[y], accI[x][y], 0, 0, 0);
+        accR[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.imI[x], o.imJ[y], accR[x][y], 0, 0, 0);
+        accI[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.imI[x], o.reJ[y], accI[x][y], 0, 0, 0);
+    }
+}
+
+// Blocks of the last K step issued before the next stage is published and
+// its fragments are read (the rest are issued after, covering the reads'
+// latency; the ones before cover the barrier's wait). Measured best: half
+// for 4-bit input (two K steps per stage), one block for 8-bit (one K step).
+template <int IN_BITS> constexpr int wg_split() { return IN_BITS == 4 ? 2 : 1; }
+
 // 16 v_mfma_i32_32x32x32_i8 of one K step over 2 x 2 tiles of 32 x 32:
 //   accR[x][y] += re_I re_J + im_I im_J,  accI[x][y] += re_I ~im_J + im_I re_J.
 __device__ __forceinline__ void wg_mfma(const WgOps &o, i32x16 (&accR)[2][2], i32x16 (&accI)[2][2])
@@ -526,30 +549,41 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
             }
         // the stage's fragments were read by the previous step (RA); unpack
         // and multiply, then publish and read the next stage
+        // The stage's fragments were read by the previous step (RA). Once
+        // its last K step is unpacked RA is free, so the next stage is
+        // published and read into RA between the first wg_split() blocks of
+        // that K step's MFMAs and the rest: the MFMAs before the barrier
+        // cover its wait, those after cover the reads' latency.
         for (int k = 0; k < nst; ++k, ++s) {
             if (issued < n_total) d_issue();
+            const bool more = s + 1 < n_total;
             // wave 3 of a diagonal tile has no quarter of its own: it keeps
             // copying and synchronising but leaves its SIMD's matrix core to
-            // the other workgroup (one uniform branch per stage, outside the
-            // MFMA chain)
-            if (write) {
-                if constexpr (ENG == ENG_F8) {
-                    wg_f8_stage(RA, accR, accI);
-                } else if constexpr (IN_BITS == 4) {
-                    wg_unpack(RA, 0, O0);
-                    wg_mfma(O0, accR, accI);
-                    wg_unpack(RA, 1, O0);
-                    wg_mfma(O0, accR, accI);
-                } else {
-                    wg8_unpack(RA, O0);
-                    wg_mfma(O0, accR, accI);
+            // the other workgroup (uniform branches outside the MFMA chains)
+            if constexpr (ENG == ENG_F8) {
+                if (write) wg_f8_stage(RA, accR, accI);
+                if (more) {
+                    prep_stage(s + 1);
+                    read_frags((s + 1) % WG_NBUF, RA);
                 }
+            } else {
+                if (write) {
+                    if constexpr (IN_BITS == 4) {
+                        wg_unpack(RA, 0, O0);
+                        wg_mfma(O0, accR, accI);
+                        wg_unpack(RA, 1, O0);
+                    } else {
+                        wg8_unpack(RA, O0);
+                    }
+                    wg_mfma_blocks<0, wg_split<IN_BITS>()>(O0, accR, accI);
+                }
+                if (more) {
+                    prep_stage(s + 1);
+                    read_frags((s + 1) % WG_NBUF, RA);
+                }
+                if (write) wg_mfma_blocks<wg_split<IN_BITS>(), 4>(O0, accR, accI);
             }
-            if (s + 1 < n_total) {
-                prep_stage(s + 1);
-                read_frags((s + 1) % WG_NBUF, RA);
-                r_advance();
-            }
+            if (more) r_advance();
         }
 
         // ---- flush. 32 x 32 MFMA result: lane l holds column l % 32 of rows
