@@ -272,6 +272,54 @@ def batch_bench(args):
     print(json.dumps(res), flush=True)
 
 
+def ingest_bench(args):
+    """Packet ingest: the LEDA gulp (N=512, 128 channels, 8192 samples) cut
+    into F-engine packets of 4 times x 16 channels x 64 inputs (4 KB payload),
+    5 % lost and shuffled; the corner turn into the gulp is timed (HBM-bound:
+    bytes = packets read + gulp written)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1411_3751_amd import Ingest
+
+    torch.cuda.set_device(0)
+    samples, _, _, meta = synth.workload("leda_gulp")
+    N, F, T = meta["n_inputs"], meta["n_chans"], meta["n_time"]
+    fmt = (4, 16, 64)
+    t0 = 5 * T
+    pk = synth.packetize(samples, t0, *fmt)
+    rng = np.random.default_rng(3)
+    pk = np.ascontiguousarray(pk[rng.permutation(len(pk))[: int(0.95 * len(pk))]])
+    d_pk = torch.from_numpy(pk.reshape(-1)).cuda()
+    gulp = torch.empty((T, F, N), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    with Ingest(dict(n_inputs=N, n_chans=F, n_time=T), *fmt) as ig:
+        for _ in range(args.warmup):
+            ig.gulp(d_pk, len(pk), t0, gulp, stream)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            ig.gulp(d_pk, len(pk), t0, gulp, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        st = ig.stats()
+    nbytes = pk.nbytes + gulp.numel()
+    res = {"metric": "packet ingest (corner turn) GB/s", "value": round(nbytes / (ms * 1e-3) / 1e9, 1),
+           "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+           "config": {"workload": "leda_gulp_packets", "n_inputs": N, "n_chans": F, "n_time": T,
+                      "packet": list(fmt), "packets": len(pk), "lost_fraction": 0.05},
+           "packets_per_s": round(len(pk) / (ms * 1e-3)), "stats": st,
+           "roofline": {"bound": "hbm", "achieved": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                        "peak": 8000.0, "unit": "GB/s",
+                        "frac": round(nbytes / (ms * 1e-3) / 8e12, 4), "traffic": None}}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,11 +341,19 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="run the batched uneven-subarray configuration instead (autotuned, "
                          "graph-captured)")
+    ap.add_argument("--ingest", action="store_true",
+                    help="time the packet ingest (corner turn of F-engine packets) instead")
     ap.add_argument("--stream-gulps", type=int, default=260)
     ap.add_argument("--dump-every", type=int, default=26)
     ap.add_argument("--pace", type=float, default=4.0,
                     help="latency run: gulps arrive at this multiple of the real-time rate")
     args = ap.parse_args()
+    if args.ingest:
+        if args.gpus != 1:
+            print("bench.py measures one GPU (--gpus %d requested)" % args.gpus, file=sys.stderr)
+            sys.exit(2)
+        ingest_bench(args)
+        return
     if args.batch:
         if args.gpus != 1:
             print("bench.py measures one GPU (--gpus %d requested)" % args.gpus, file=sys.stderr)

@@ -255,6 +255,69 @@ int xeng_stream_gulps(const xeng_stream *s, int64_t *out);
 /* Wait for all work of the stream and release it. NULL is a no-op. */
 int xeng_stream_destroy(xeng_stream *s);
 
+/*
+ * ---- Packet ingest (Section 2.3: the F-engine boards send UDP packets of a
+ * header and a payload of channelised samples to the GPU servers; Section
+ * 2.4: the CPU layer captures them and completes the corner turn into the
+ * X-engine's [time][channel][input] order; missing packets are counted, not
+ * corrected). The paper's payload layout is not recoverable from its text,
+ * so the format is this library's own:
+ *
+ *   header, 16 bytes, little-endian:
+ *     uint64 t0       first time sample of the packet (absolute)
+ *     uint16 chan0    first channel
+ *     uint16 input0   first input
+ *     uint32 magic    XENG_PACKET_MAGIC
+ *   payload: pkt_time x pkt_chans x pkt_inputs samples, [time][chan][input],
+ *   in the subarray's sample format (1 byte per 4+4-bit sample, 2 for 8-bit)
+ *   packet stride: 16 + payload bytes rounded up to a multiple of 16.
+ *
+ * A gulp [gulp_t0, gulp_t0 + n_time) expects one packet per (time block,
+ * channel block, input block): n_time / pkt_time x n_chans / pkt_chans x
+ * n_inputs / pkt_inputs packets, which must divide exactly. The ingest
+ * writes every valid packet's samples into the gulp buffer, zero-fills the
+ * blocks whose packet did not arrive (zeros add nothing to any sum), and
+ * counts received, missing, duplicate and rejected packets (bad magic, not
+ * aligned to the blocks, or outside the gulp).
+ */
+#define XENG_PACKET_MAGIC 0x4C454441u /* "LEDA" */
+
+typedef struct {
+    int32_t pkt_time;   /* time samples per packet */
+    int32_t pkt_chans;  /* channels per packet */
+    int32_t pkt_inputs; /* inputs per packet */
+} xeng_packet_format;
+
+typedef struct xeng_ingest xeng_ingest; /* opaque, library-owned */
+
+typedef struct {
+    int64_t received;   /* packets written into the gulp */
+    int64_t missing;    /* expected packets that did not arrive (zero-filled) */
+    int64_t duplicate;  /* second and later copies of a block (ignored) */
+    int64_t rejected;   /* bad magic, misaligned, or outside the gulp */
+} xeng_ingest_stats;
+
+/* Create an ingest engine for gulps of `sub` (n_time samples) and packets of
+ * `fmt`. Allocates a small device bitmap and counters. Errors: XENG_EINVAL
+ * (sizes that do not divide), XENG_ENOMEM, XENG_EHIP. */
+int xeng_ingest_create(const xeng_subarray *sub, const xeng_packet_format *fmt, xeng_ingest **out);
+
+/* Bytes between consecutive packets in a packet buffer. */
+int xeng_ingest_packet_stride(const xeng_ingest *ig, int64_t *out);
+
+/* Scatter n_packets packets (device buffer, packet stride apart, any order)
+ * into the device gulp buffer d_gulp for the gulp starting at absolute
+ * time gulp_t0, zero-fill what is missing and update the counters; all
+ * enqueued on hip_stream (a hipStream_t). d_gulp is fully written. */
+int xeng_ingest_gulp(xeng_ingest *ig, const void *d_packets, int64_t n_packets, int64_t gulp_t0,
+                     void *d_gulp, void *hip_stream);
+
+/* Wait for the last gulp's ingest on its stream and return its counters. */
+int xeng_ingest_stats_get(xeng_ingest *ig, xeng_ingest_stats *out);
+
+/* Release the engine (waits for its last stream). NULL is a no-op. */
+int xeng_ingest_destroy(xeng_ingest *ig);
+
 /* Static text for an XENG_* code. */
 const char *xeng_strerror(int code);
 

@@ -8,6 +8,7 @@ from .xeng import (  # noqa: F401
     ENGINE_I8,
     Correlator,
     Graph,
+    Ingest,
     Stream,
     Subarray,
     XengError,

@@ -27,13 +27,26 @@ EXPORTS = (
     "xeng_stream_gulp_times", "xeng_stream_gulps", "xeng_stream_destroy",
     "xeng_autotune", "xeng_graph_create", "xeng_graph_launch", "xeng_graph_destroy",
     "xeng_set_fast_autos", "xeng_dump_fast_autos",
+    "xeng_ingest_create", "xeng_ingest_packet_stride", "xeng_ingest_gulp", "xeng_ingest_stats_get",
+    "xeng_ingest_destroy",
 )
+PACKET_MAGIC = 0x4C454441
 
 
 class XengError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__("xeng error %d: %s" % (code, msg))
         self.code = code
+
+
+class PacketFormat(ctypes.Structure):
+    _fields_ = [("pkt_time", ctypes.c_int32), ("pkt_chans", ctypes.c_int32),
+                ("pkt_inputs", ctypes.c_int32)]
+
+
+class IngestStats(ctypes.Structure):
+    _fields_ = [("received", ctypes.c_int64), ("missing", ctypes.c_int64),
+                ("duplicate", ctypes.c_int64), ("rejected", ctypes.c_int64)]
 
 
 class Subarray(ctypes.Structure):
@@ -92,6 +105,17 @@ def load():
     lib.xeng_stream_gulps.restype = i32
     lib.xeng_stream_destroy.argtypes = [vp]
     lib.xeng_stream_destroy.restype = i32
+    lib.xeng_ingest_create.argtypes = [ctypes.POINTER(Subarray), ctypes.POINTER(PacketFormat),
+                                       ctypes.POINTER(vp)]
+    lib.xeng_ingest_create.restype = i32
+    lib.xeng_ingest_packet_stride.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.xeng_ingest_packet_stride.restype = i32
+    lib.xeng_ingest_gulp.argtypes = [vp, vp, i64, i64, vp, vp]
+    lib.xeng_ingest_gulp.restype = i32
+    lib.xeng_ingest_stats_get.argtypes = [vp, ctypes.POINTER(IngestStats)]
+    lib.xeng_ingest_stats_get.restype = i32
+    lib.xeng_ingest_destroy.argtypes = [vp]
+    lib.xeng_ingest_destroy.restype = i32
     lib.xeng_set_fast_autos.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32), i32]
     lib.xeng_set_fast_autos.restype = i32
     lib.xeng_dump_fast_autos.argtypes = [vp, pp, i32, i32]
@@ -367,6 +391,61 @@ class Graph:
         if getattr(self, "_g", None) and self._g.value:
             rc = self._lib.xeng_graph_destroy(self._g)
             self._g = ctypes.c_void_p()
+            _check(rc)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ingest:
+    """Corner turn of F-engine packets (format in include/xeng.h) into gulps."""
+
+    def __init__(self, subarray, pkt_time: int, pkt_chans: int, pkt_inputs: int):
+        s = subarray if isinstance(subarray, Subarray) else Subarray(
+            int(subarray["n_inputs"]), int(subarray["n_chans"]), int(subarray["n_time"]),
+            int(subarray.get("in_bits", 4)), int(subarray.get("engine", ENGINE_I8)))
+        self.sub = s
+        self._lib = load()
+        self._ig = ctypes.c_void_p()
+        fmt = PacketFormat(pkt_time, pkt_chans, pkt_inputs)
+        _check(self._lib.xeng_ingest_create(ctypes.byref(s), ctypes.byref(fmt), ctypes.byref(self._ig)))
+        v = ctypes.c_int64()
+        _check(self._lib.xeng_ingest_packet_stride(self._ig, ctypes.byref(v)))
+        self.stride = v.value
+
+    def gulp(self, packets, n_packets: int, gulp_t0: int, out, stream=None):
+        """packets: device uint8 tensor of n_packets * stride bytes; out: device gulp buffer."""
+        if packets is not None and packets.numel() < n_packets * self.stride:
+            raise ValueError("packet buffer shorter than n_packets * stride")
+        shape = (self.sub.n_time, self.sub.n_chans, self.sub.n_inputs)
+        if self.sub.in_bits == 8:
+            shape = shape + (2,)
+        if tuple(out.shape) != shape or not out.is_cuda or not out.is_contiguous() \
+                or out.element_size() != 1:
+            raise ValueError("out must be a contiguous 1-byte device tensor %s" % (shape,))
+        _check(self._lib.xeng_ingest_gulp(self._ig, ctypes.c_void_p(packets.data_ptr() if n_packets else 0),
+                                          int(n_packets), int(gulp_t0), ctypes.c_void_p(out.data_ptr()),
+                                          ctypes.c_void_p(_stream_handle(stream))))
+
+    def stats(self) -> dict:
+        st = IngestStats()
+        _check(self._lib.xeng_ingest_stats_get(self._ig, ctypes.byref(st)))
+        return dict(received=st.received, missing=st.missing, duplicate=st.duplicate,
+                    rejected=st.rejected)
+
+    def close(self):
+        if getattr(self, "_ig", None) and self._ig.value:
+            rc = self._lib.xeng_ingest_destroy(self._ig)
+            self._ig = ctypes.c_void_p()
             _check(rc)
 
     def __enter__(self):

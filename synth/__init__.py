@@ -7,6 +7,7 @@ inputs from it without sharing any of the method.
 """
 from .gen import (  # noqa: F401
     BATCH_SHAPES,
+    PACKET_MAGIC,
     SEED_BASE,
     TONE_AMP,
     TONE_NU,
@@ -16,6 +17,8 @@ from .gen import (  # noqa: F401
     fixed_tone,
     pack4,
     pack8,
+    packet_stride,
+    packetize,
     stream,
     thresholds,
     tone_channels,

@@ -198,3 +198,39 @@ def workload(name: str, subarray: int = 0, n_time: int | None = None,
                              components=components)
     meta = dict(w, n_time=T, n_chans=F, n_inputs=N, seed=seed)
     return samples, re, im, meta
+
+
+PACKET_MAGIC = 0x4C454441  # "LEDA", the packet header's magic word
+
+
+def packet_stride(pkt_time: int, pkt_chans: int, pkt_inputs: int, in_bits: int = 4) -> int:
+    payload = pkt_time * pkt_chans * pkt_inputs * (in_bits // 4)
+    return 16 + (payload + 15) // 16 * 16
+
+
+def packetize(samples: np.ndarray, t0: int, pkt_time: int, pkt_chans: int, pkt_inputs: int,
+              in_bits: int = 4) -> np.ndarray:
+    """Cut a stream slice [T][F][N](x2) starting at absolute time t0 into
+    F-engine packets (16-byte header: uint64 t0, uint16 chan0, uint16 input0,
+    uint32 magic; payload [pkt_time][pkt_chans][pkt_inputs] samples), in
+    (time block, channel block, input block) order. Returns uint8
+    [n_packets][stride]."""
+    s = np.ascontiguousarray(samples).view(np.uint8)
+    T, F, N = samples.shape[:3]
+    bps = in_bits // 4
+    s = s.reshape(T, F, N * bps)
+    nt, nf, ni = T // pkt_time, F // pkt_chans, N // pkt_inputs
+    if nt * pkt_time != T or nf * pkt_chans != F or ni * pkt_inputs != N:
+        raise ValueError("packet blocks must divide the stream slice")
+    stride = packet_stride(pkt_time, pkt_chans, pkt_inputs, in_bits)
+    out = np.zeros((nt, nf, ni, stride), np.uint8)
+    blk = s.reshape(nt, pkt_time, nf, pkt_chans, ni, pkt_inputs * bps).transpose(0, 2, 4, 1, 3, 5)
+    payload = pkt_time * pkt_chans * pkt_inputs * bps
+    out[..., 16:16 + payload] = blk.reshape(nt, nf, ni, payload)
+    hdr = np.zeros((nt, nf, ni, 2), np.uint64)
+    tb, fb, ib = np.meshgrid(np.arange(nt), np.arange(nf), np.arange(ni), indexing="ij")
+    hdr[..., 0] = (t0 + tb * pkt_time).astype(np.uint64)
+    hdr[..., 1] = ((fb * pkt_chans).astype(np.uint64) | ((ib * pkt_inputs).astype(np.uint64) << 16)
+                   | (np.uint64(PACKET_MAGIC) << np.uint64(32)))
+    out[..., :16] = hdr.view(np.uint8).reshape(nt, nf, ni, 16)
+    return out.reshape(nt * nf * ni, stride)
