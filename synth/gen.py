@@ -234,3 +234,49 @@ def packetize(samples: np.ndarray, t0: int, pkt_time: int, pkt_chans: int, pkt_i
                    | (np.uint64(PACKET_MAGIC) << np.uint64(32)))
     out[..., :16] = hdr.view(np.uint8).reshape(nt, nf, ni, 16)
     return out.reshape(nt * nf * ni, stride)
+
+
+# F-engine input: real 8-bit ADC samples (Section 2.2: an 8-bit, 16-input ADC
+# clocked at 196.608 MHz feeds the PFB). Gaussian receiver noise plus
+# continuous-wave tones, the test signal the paper injects into an assembled
+# F-engine (Section 5). Frequencies are in channel units (cycles per sample
+# times the FFT length), so a tone at 1400.0 sits at the centre of channel 1400.
+ADC_SIGMA = 16.0
+ADC_FFT = 8192
+ADC_TONES = ((1400.0, 40.0), (2100.25, 24.0), (3000.5, 12.0), (3600.0, 90.0))
+
+
+def adc(seed: int, n_inputs: int, n_samples: int, sigma: float = ADC_SIGMA, tones=ADC_TONES,
+        n_fft: int = ADC_FFT) -> np.ndarray:
+    """int8 ``[n_inputs][n_samples]`` ADC samples: round(sigma g + sum_k A_k
+    cos(2 pi f_k s / n_fft + phi_kn)), clipped to [-128, 127]; g ~ N(0, 1) from
+    numpy's PCG64 seeded with ``seed``; phase phi_kn = 2 pi (0.37 n + 0.11 k)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = sigma * rng.standard_normal((n_inputs, n_samples))
+    s = np.arange(n_samples, dtype=np.float64)
+    for k, (f, amp) in enumerate(tones or ()):
+        ph = 2.0 * np.pi * (0.37 * np.arange(n_inputs) + 0.11 * k)
+        x += amp * np.cos(2.0 * np.pi * f * s[None, :] / n_fft + ph[:, None])
+    return np.clip(np.rint(x), -128, 127).astype(np.int8)
+
+
+def adc_device(seed: int, n_inputs: int, n_samples: int, device, sigma: float = ADC_SIGMA,
+               tones=ADC_TONES, n_fft: int = ADC_FFT):
+    """The same recipe as :func:`adc` drawn on a torch device (torch's own
+    generator, so the values differ from :func:`adc`; the law is the same).
+    Built one input row block at a time to bound the float32 temporaries."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    out = torch.empty((n_inputs, n_samples), dtype=torch.int8, device=device)
+    s = torch.arange(n_samples, dtype=torch.float64, device=device)
+    step = max(1, (1 << 26) // max(1, n_samples))
+    for n0 in range(0, n_inputs, step):
+        n1 = min(n_inputs, n0 + step)
+        x = sigma * torch.randn((n1 - n0, n_samples), generator=g, device=device)
+        for k, (f, amp) in enumerate(tones or ()):
+            ph = 2.0 * np.pi * (0.37 * torch.arange(n0, n1, device=device, dtype=torch.float64) + 0.11 * k)
+            cyc = torch.remainder(f * s / n_fft, 1.0)
+            x += (amp * torch.cos(2.0 * np.pi * cyc[None, :] + ph[:, None])).float()
+        out[n0:n1] = torch.clamp(torch.round(x), -128, 127).to(torch.int8)
+    return out
