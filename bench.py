@@ -33,16 +33,18 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1411_3751_amd", "csrc", f)
                   for f in ("xeng.hip", "xcorr_wg.h", "xcorr_i8.h")]
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(files=None) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    srcs = KERNEL_SOURCES if files is None else [
+        os.path.join(ROOT, "paper_1411_3751_amd", "csrc", f) for f in files]
+    for f in srcs:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def hbm_traffic(kernel: str, workload: str):
+def hbm_traffic(kernel: str, workload: str, files=None):
     """HBM bytes per launch from the committed counter summary, or None.
 
     The summary holds FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the
@@ -60,7 +62,7 @@ def hbm_traffic(kernel: str, workload: str):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("source_sha256") != kernel_source_hash():
+    if kv.get("source_sha256") != kernel_source_hash(files):
         return None
     try:
         return int(float(kv["hbm_bytes_per_launch"]))
@@ -320,6 +322,96 @@ def ingest_bench(args):
     print(json.dumps(res), flush=True)
 
 
+FENGINE_CFG = dict(n_inputs=512, chan0=1250, n_chans=2398, n_spectra=64, gain=22.0, seed=7)
+ADC_HZ = 196.608e6               # the paper's ADC sample clock (Section 2.2)
+FE_P, FE_TAPS = 8192, 4
+# algorithmic operations per spectrum of one input: the FIR's multiply-adds
+# (2 taps P) plus the usual 2.5 P log2 P flops of a P-point real FFT
+FE_OPS_PER_SPECTRUM = 2 * FE_TAPS * FE_P + 2.5 * FE_P * 13
+PEAK_FP32_VECTOR = 157.3e12      # MI355X vector fp32, flop/s
+
+
+def fengine_cpu_baseline(adc_rows, gain, chan0, n_chans, budget_s=12.0):
+    """The reference F-engine on a bounded sample: whole spectra of a few inputs."""
+    from oracle import fengine as fe
+    n_rows, S = adc_rows.shape
+    n_m = S // FE_P - (FE_TAPS - 1)
+    t0 = time.perf_counter()
+    done = 0
+    while time.perf_counter() - t0 < budget_s:
+        m = done % n_m
+        fe.fengine(adc_rows, 0, gain, chan0, n_chans, spectra=[m])
+        done += 1
+    dt = time.perf_counter() - t0
+    samples = done * n_rows * FE_P
+    return {"value": round(samples / dt / 1e9, 4), "unit": "Gsamples/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d spectra of %d inputs (%d ADC samples each), %.1f s" % (
+                done, n_rows, FE_P, dt)}
+
+
+def fengine_bench(args):
+    """F-engine: 512 ADC inputs, 64 spectra per call (8192 new samples each),
+    PFB + FFT + requantisation of channels 1250..3647 (30-88 MHz) into the
+    X-engine's 4+4-bit layout. Input resident in HBM; each call is one launch."""
+    import torch
+
+    import synth
+    from paper_1411_3751_amd import FEngine
+
+    torch.cuda.set_device(0)
+    c = FENGINE_CFG
+    N, M, F = c["n_inputs"], c["n_spectra"], c["n_chans"]
+    S = FE_P * (M + FE_TAPS - 1)
+    log("generating %d x %d ADC samples on the device ..." % (N, S))
+    d_adc = synth.adc_device(c["seed"], N, S, "cuda")
+    out = torch.empty((M, F, N), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    with FEngine(N, c["chan0"], F, c["gain"]) as f:
+        for _ in range(args.warmup):
+            f.run(d_adc, M, out, stream=stream)
+        torch.cuda.synchronize()
+        n = args.steps
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
+        k_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                for _ in range(n)]
+        t_start.record(stream)
+        for k in range(n):
+            k_ev[k][0].record(stream)
+            f.run(d_adc, M, out, stream=stream)
+            k_ev[k][1].record(stream)
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        group = f.group
+    ms_step = t_start.elapsed_time(t_end) / n
+    ms_kernel = sum(a.elapsed_time(b) for a, b in k_ev) / n
+    samples = N * M * FE_P
+    value = samples / (ms_step * 1e-3)
+    ops = N * M * FE_OPS_PER_SPECTRUM
+    achieved = ops / (ms_kernel * 1e-3)
+    res = {"metric": "F-engine ADC samples/s (Gsamples/s) at N=512; real-time factor at 196.608 MS/s",
+           "value": round(value / 1e9, 2), "unit": "Gsamples/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "fengine_512", "n_inputs": N, "n_spectra": M,
+                      "chan0": c["chan0"], "n_chans": F, "fft": FE_P, "taps": FE_TAPS,
+                      "gain": c["gain"], "group": group},
+           "rtf": round(value / (N * ADC_HZ), 2),
+           "spectra_per_s": round(N * M / (ms_step * 1e-3)),
+           "ms_kernel": round(ms_kernel, 4),
+           "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 2),
+                        "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
+                        "frac": round(achieved / PEAK_FP32_VECTOR, 4),
+                        "traffic": hbm_traffic("fengine_kernel", "fengine_512",
+                                               ["xeng_fengine.h"])}}
+    if not args.no_cpu:
+        log("timing the CPU reference F-engine on a sample ...")
+        rows = d_adc[:4, :FE_P * (FE_TAPS + 3)].cpu().numpy()
+        res["cpu_baseline"] = fengine_cpu_baseline(rows, c["gain"], c["chan0"], F)
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -343,11 +435,19 @@ def main():
                          "graph-captured)")
     ap.add_argument("--ingest", action="store_true",
                     help="time the packet ingest (corner turn of F-engine packets) instead")
+    ap.add_argument("--fengine", action="store_true",
+                    help="time the F-engine (PFB + FFT + 4+4-bit requantisation) instead")
     ap.add_argument("--stream-gulps", type=int, default=260)
     ap.add_argument("--dump-every", type=int, default=26)
     ap.add_argument("--pace", type=float, default=4.0,
                     help="latency run: gulps arrive at this multiple of the real-time rate")
     args = ap.parse_args()
+    if args.fengine:
+        if args.gpus != 1:
+            print("bench.py measures one GPU (--gpus %d requested)" % args.gpus, file=sys.stderr)
+            sys.exit(2)
+        fengine_bench(args)
+        return
     if args.ingest:
         if args.gpus != 1:
             print("bench.py measures one GPU (--gpus %d requested)" % args.gpus, file=sys.stderr)

@@ -318,6 +318,58 @@ int xeng_ingest_stats_get(xeng_ingest *ig, xeng_ingest_stats *out);
 /* Release the engine (waits for its last stream). NULL is a no-op. */
 int xeng_ingest_destroy(xeng_ingest *ig);
 
+/*
+ * ---- F-engine (Section 2.2: a 4-tap, 8192-point polyphase filter bank, an
+ * FIR filter with a Hamming window and 18-bit coefficients followed by an FFT
+ * that halves the data at each stage; one band-average digital gain; the
+ * result requantised to 4+4 bits; a contiguous group of channels kept).
+ *
+ * For input n and spectrum m (samples [8192 m, 8192 (m + 4)) of the input):
+ *   c[l]  = clip(rint(2^17 w[l] sinc((l - 16383.5) / 8192)), -2^17, 2^17 - 1),
+ *           l < 32768, w the symmetric Hamming window of length 32768;
+ *   y[k]  = sum_{tap<4} c[8192 tap + k] x_n[8192 (m + tap) + k], k < 8192
+ *           (exact integers);
+ *   Y[ch] = gain 2^-17 / 8192 sum_k y[k] exp(-2 pi i k ch / 8192) (fp32);
+ *   out[m][ch - chan0][n] = clip(rint(Re Y), -8, 7) << 4
+ *                         | (clip(rint(Im Y), -8, 7) & 15),
+ * the X-engine's 4+4-bit [time][channel][input] input (rint: half to even).
+ * Channel ch covers ch x 24.0 kHz at the paper's 196.608 MHz sample clock.
+ */
+#define XENG_FENGINE_FFT 8192
+#define XENG_FENGINE_TAPS 4
+#define XENG_FENGINE_CHANS 4096 /* channels 0 .. 4095 (DC to just below Nyquist) */
+
+typedef struct xeng_fengine xeng_fengine; /* opaque, library-owned */
+
+typedef struct xeng_fengine_config {
+    int32_t n_inputs; /* ADC inputs, 1 .. 65535 */
+    int32_t chan0;    /* first channel kept, >= 0 */
+    int32_t n_chans;  /* channels kept; chan0 + n_chans <= XENG_FENGINE_CHANS */
+    float gain;       /* the one band-average digital gain, > 0 and finite */
+} xeng_fengine_config;
+
+/* Create an F-engine on the current device: builds the coefficient and
+ * twiddle tables in device memory. Errors: XENG_EINVAL (sizes, gain),
+ * XENG_ENOMEM. */
+int xeng_fengine_create(const xeng_fengine_config *cfg, xeng_fengine **out);
+
+/* Inputs handled by one workgroup (1, 2, 4, 8 or 16; d_out must be aligned
+ * to it). Returns it, or XENG_EINVAL (negative) for NULL. */
+int xeng_fengine_group(const xeng_fengine *fe);
+
+/* Channelise n_spectra spectra of every input, enqueued on hip_stream (a
+ * hipStream_t; NULL = default stream). d_adc: device int8 [n_inputs][adc_stride]
+ * samples, row start and adc_stride multiples of 8, adc_stride >=
+ * (n_spectra + 3) 8192. d_out: device uint8 [n_spectra][n_chans][n_inputs],
+ * fully written. d_spec: NULL, or device float2 [n_spectra][n_chans][n_inputs]
+ * (8-byte aligned) that receives (Re Y, Im Y) before rounding. Errors:
+ * XENG_EINVAL (NULL pointers, sizes, alignment), XENG_EHIP (launch). */
+int xeng_fengine_run(xeng_fengine *fe, const int8_t *d_adc, int64_t adc_stride, int64_t n_spectra,
+                     uint8_t *d_out, void *d_spec, void *hip_stream);
+
+/* Release the engine (synchronises the device first). NULL is a no-op. */
+int xeng_fengine_destroy(xeng_fengine *fe);
+
 /* Static text for an XENG_* code. */
 const char *xeng_strerror(int code);
 

@@ -737,3 +737,4 @@ int xeng_plan_describe(const xeng_ctx *ctx, char *buf, size_t len)
 #include "xeng_stream.h"
 #include "xeng_tune.h"
 #include "xeng_ingest.h"
+#include "xeng_fengine.h"

@@ -1,0 +1,395 @@
+// F-engine: polyphase filter bank, FFT and requantisation to 4+4 bits
+// (Section 2.2: a 4-tap, 8192-point PFB made of an FIR filter with a Hamming
+// window and 18-bit coefficients followed by an FFT whose stages halve the
+// data, 24.0 kHz channels; one band-average digital gain; requantisation of
+// the 18+18-bit values to 4+4 bits; a contiguous group of channels selected).
+// Part of the libxeng.so translation unit (included by xeng.hip).
+//
+// Definition computed (spectrum m of input n, k < P = 8192, L = 4 P):
+//   c[l]  = clip(rint(2^17 w[l] sinc((l - (L-1)/2) / P)), -2^17, 2^17 - 1),
+//           w the symmetric Hamming window of length L
+//   y[k]  = sum_tap c[tap P + k] x[(m + tap) P + k]          (exact, int32)
+//   Y[ch] = gain 2^-17 / P sum_k y[k] exp(-2 pi i k ch / P)    (fp32)
+//   code  = clip(rint(Re Y), -8, 7) << 4 | clip(rint(Im Y), -8, 7) (nibbles)
+// written to out[m][ch - chan0][n], the X-engine's [time][channel][input].
+//
+// One workgroup of 256 threads takes one spectrum of G consecutive inputs,
+// one input after the other:
+//   * FIR on 16-byte loads of contiguous samples, z[j] = y[2j] + i y[2j+1]
+//     written to LDS;
+//   * the P-point real FFT as a 4096-point complex FFT of z: three radix-16
+//     Stockham passes, 16 points per thread, exchanged through one padded LDS
+//     buffer (index i at i + i/16 keeps the strided writes conflict-free);
+//     the pass twiddles stay in registers for the whole workgroup;
+//   * real-FFT split Y[c] = (Z[c] + conj Z[H-c]) / 2 - i exp(-2 pi i c / P)
+//     (Z[c] - conj Z[H-c]) / 2 for the selected channels, requantised;
+//   * the G codes of each channel collect in LDS and leave as one G-byte
+//     store per channel.
+// Workgroups are numbered so that the consecutive ones each XCD runs hold
+// consecutive inputs of one spectrum, so partial output lines meet in that
+// XCD's L2.
+#pragma once
+
+namespace xeng {
+
+constexpr int FE_P = 8192;                 // FFT points (real samples per spectrum)
+constexpr int FE_H = FE_P / 2;             // complex FFT points
+constexpr int FE_TAPS = 4;
+constexpr int FE_THREADS = 256;            // = FE_H / 16 radix-16 butterflies
+constexpr int FE_LDS = FE_H + FE_H / 16;   // padded complex slots
+constexpr int FE_MAX_GROUP = 16;
+constexpr int FE_CODE_LDS = 30720;         // bytes of LDS for the codes of a group
+
+struct FeArgs {
+    const int8_t *adc;     // [N][stride] ADC samples
+    int64_t adc_stride;
+    const int32_t *coef;   // [taps P] 18-bit coefficients
+    const float2 *tw;      // [FE_H] exp(-2 pi i k / FE_H)
+    const float2 *tw_r;    // [FE_H] exp(-2 pi i c / FE_P)
+    uint8_t *out;          // [n_spectra][n_chans][N]
+    float2 *spec;          // optional [n_spectra][n_chans][N] scaled values, or null
+    int32_t n_inputs, n_chans, chan0, group;
+    int32_t n_groups;      // n_inputs / group
+    int32_t n_blocks;      // n_spectra * n_groups
+    float scale;           // gain 2^-17 / P
+};
+
+__device__ __forceinline__ int fe_pad(int i) { return i + (i >> 4); }
+
+__device__ __forceinline__ float2 fe_cmul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// a * exp(-2 pi i e / 16) for a compile-time e
+template <int E>
+__device__ __forceinline__ float2 fe_w16(float2 a)
+{
+    constexpr float C1 = 0.92387953251128674f, S1 = 0.38268343236508978f, R = 0.70710678118654752f;
+    constexpr int e = E & 15;
+    if constexpr (e == 0) return a;
+    else if constexpr (e == 4) return make_float2(a.y, -a.x);
+    else if constexpr (e == 8) return make_float2(-a.x, -a.y);
+    else if constexpr (e == 12) return make_float2(-a.y, a.x);
+    else if constexpr (e == 2) return make_float2(R * (a.x + a.y), R * (a.y - a.x));
+    else if constexpr (e == 6) return make_float2(R * (a.y - a.x), -R * (a.x + a.y));
+    else {
+        // (c, s) = (cos, sin)(2 pi e / 16) from the first-octant values
+        constexpr float c = (e == 1 || e == 15) ? C1 : (e == 3 || e == 13) ? S1
+                          : (e == 5 || e == 11) ? -S1 : (e == 7 || e == 9) ? -C1
+                          : (e == 10) ? -R : (e == 14) ? R : 0.f;
+        constexpr float s = (e == 1 || e == 7) ? S1 : (e == 3 || e == 5) ? C1
+                          : (e == 9 || e == 15) ? -S1 : (e == 11 || e == 13) ? -C1
+                          : (e == 10) ? -R : (e == 14) ? -R : 0.f;
+        // multiply by (c - i s)
+        return make_float2(a.x * c + a.y * s, a.y * c - a.x * s);
+    }
+}
+
+// in-place 4-point DFT, X[k] = sum_n a[n] exp(-2 pi i n k / 4)
+__device__ __forceinline__ void fe_dft4(float2 &a0, float2 &a1, float2 &a2, float2 &a3)
+{
+    const float2 t0 = make_float2(a0.x + a2.x, a0.y + a2.y);
+    const float2 t1 = make_float2(a0.x - a2.x, a0.y - a2.y);
+    const float2 t2 = make_float2(a1.x + a3.x, a1.y + a3.y);
+    const float2 t3 = make_float2(a1.y - a3.y, a3.x - a1.x);  // -i (a1 - a3)
+    a0 = make_float2(t0.x + t2.x, t0.y + t2.y);
+    a2 = make_float2(t0.x - t2.x, t0.y - t2.y);
+    a1 = make_float2(t1.x + t3.x, t1.y + t3.y);
+    a3 = make_float2(t1.x - t3.x, t1.y - t3.y);
+}
+
+template <int K1, int N2>
+__device__ __forceinline__ void fe_tw_inner(float2 (&v)[16])
+{
+    v[4 * K1 + N2] = fe_w16<K1 * N2>(v[4 * K1 + N2]);
+}
+
+// 16-point DFT, natural order in and out: n = 4 n1 + n2, k = k1 + 4 k2
+__device__ __forceinline__ void fe_dft16(float2 (&v)[16])
+{
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) fe_dft4(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+    // v[4 k1 + n2] now holds the n1-transform; twiddle exp(-2 pi i n2 k1 / 16)
+    fe_tw_inner<1, 1>(v); fe_tw_inner<1, 2>(v); fe_tw_inner<1, 3>(v);
+    fe_tw_inner<2, 1>(v); fe_tw_inner<2, 2>(v); fe_tw_inner<2, 3>(v);
+    fe_tw_inner<3, 1>(v); fe_tw_inner<3, 2>(v); fe_tw_inner<3, 3>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) fe_dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    // v[4 k1 + k2] = X[k1 + 4 k2]: reorder
+    float2 t[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) t[k1 + 4 * k2] = v[4 * k1 + k2];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = t[k];
+}
+
+__global__ __launch_bounds__(FE_THREADS) void fengine_kernel(FeArgs a)
+{
+    __shared__ float2 z[FE_LDS];
+    extern __shared__ __align__(16) uint8_t fe_codes[];  // [n_chans][group]
+    const int t = threadIdx.x;
+
+    // workgroup number -> (spectrum, input group); the dispatcher deals
+    // workgroups round-robin over 8 XCDs, so hand each XCD a contiguous range
+    const int b = blockIdx.x, nb = a.n_blocks;
+    const int xcd = b & 7, q8 = nb >> 3, r8 = nb & 7;
+    const int logical = xcd * q8 + (xcd < r8 ? xcd : r8) + (b >> 3);
+    const int64_t m = logical / a.n_groups;
+    const int n0 = (logical - (int)m * a.n_groups) * a.group;
+
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)a.coef, (short)0, FE_TAPS * FE_P * 4, 0x00020000);
+    // pass-3 twiddles exp(-2 pi i t r / 4096), fixed per thread
+    float2 w3[15];
+#pragma unroll
+    for (int r = 1; r < 16; ++r) w3[r - 1] = a.tw[t * r];
+
+    for (int g = 0; g < a.group; ++g) {
+        const int n = n0 + g;
+        float2 v[16];
+        // FIR on contiguous samples: thread t takes positions [16t, 16t + 16)
+        // and [4096 + 16t, 4096 + 16t + 16) of every tap block, i.e. complex
+        // points 8t + e and 2048 + 8t + e (e < 8); 16-byte buffer loads, the
+        // next tap's coefficients in flight while this tap accumulates
+        const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(a.adc + (int64_t)n * a.adc_stride + m * FE_P), (short)0, FE_TAPS * FE_P, 0x00020000);
+        {
+            uint32_t xs[FE_TAPS][2][4];
+#pragma unroll
+            for (int tap = 0; tap < FE_TAPS; ++tap)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const auto w = __builtin_amdgcn_raw_buffer_load_b128(rx, 16 * t, tap * FE_P + 4096 * h, 0);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) xs[tap][h][q] = w[q];
+                }
+            int acc[2][16] = {};
+            uint32_t cb[2][2][16];
+            auto load_coef = [&](int buf, int tap) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const auto w = __builtin_amdgcn_raw_buffer_load_b128(
+                            rc, 64 * t + 16 * q, 4 * (tap * FE_P + 4096 * h), 0);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) cb[buf][h][4 * q + e] = w[e];
+                    }
+            };
+            load_coef(0, 0);
+#pragma unroll
+            for (int tap = 0; tap < FE_TAPS; ++tap) {
+                if (tap + 1 < FE_TAPS) load_coef((tap + 1) & 1, tap + 1);
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const int xv = (int)(int8_t)(xs[tap][h][i >> 2] >> (8 * (i & 3)));
+                        acc[h][i] += __mul24((int)cb[tap & 1][h][i], xv);
+                    }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    z[fe_pad(2048 * h + 8 * t + e)] =
+                        make_float2((float)acc[h][2 * e], (float)acc[h][2 * e + 1]);
+        }
+        __syncthreads();
+        // pass 1 (span 1): points t + 256 r, no twiddles; output index 16 t + r
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = z[fe_pad(t + 256 * r)];
+        fe_dft16(v);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) z[fe_pad(16 * t + r)] = v[r];
+        __syncthreads();
+        // pass 2 (span 16)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = z[fe_pad(t + 256 * r)];
+        // pass-2 twiddles exp(-2 pi i (t%16) r / 256): 256 table entries
+#pragma unroll
+        for (int r = 1; r < 16; ++r) v[r] = fe_cmul(v[r], a.tw[(t & 15) * r * 16]);
+        fe_dft16(v);
+        __syncthreads();
+        {
+            const int base = (t >> 4) * 256 + (t & 15);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) z[fe_pad(base + 16 * r)] = v[r];
+        }
+        __syncthreads();
+        // pass 3 (span 256): output in natural order, Z[t + 256 r]
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = z[fe_pad(t + 256 * r)];
+#pragma unroll
+        for (int r = 1; r < 16; ++r) v[r] = fe_cmul(v[r], w3[r - 1]);
+        fe_dft16(v);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) z[fe_pad(t + 256 * r)] = v[r];
+        __syncthreads();
+        // real-FFT split, gain, requantisation of the selected channels
+        for (int q = t; q < a.n_chans; q += FE_THREADS) {
+            const int c = a.chan0 + q;
+            const float2 zc = z[fe_pad(c)];
+            const float2 zn = z[fe_pad((FE_H - c) & (FE_H - 1))];
+            const float ex = zc.x + zn.x, ey = zc.y - zn.y;        // 2 E
+            const float2 d = make_float2(zc.x - zn.x, zc.y + zn.y); // 2 D
+            const float2 wd = fe_cmul(a.tw_r[c], d);
+            // Y = E - i W D; the halves fold into the scale
+            const float yr = (0.5f * a.scale) * (ex + wd.y);
+            const float yi = (0.5f * a.scale) * (ey - wd.x);
+            if (a.spec)
+                a.spec[((int64_t)m * a.n_chans + q) * a.n_inputs + n] = make_float2(yr, yi);
+            const int qr = (int)fminf(fmaxf(rintf(yr), -8.f), 7.f);
+            const int qi = (int)fminf(fmaxf(rintf(yi), -8.f), 7.f);
+            fe_codes[q * a.group + g] = (uint8_t)(((qr & 15) << 4) | (qi & 15));
+        }
+        __syncthreads();
+    }
+
+    // one G-byte store per channel
+    uint8_t *o = a.out + (int64_t)m * a.n_chans * a.n_inputs + n0;
+    for (int q = t; q < a.n_chans; q += FE_THREADS) {
+        const uint8_t *s = fe_codes + q * a.group;
+        uint8_t *d = o + (int64_t)q * a.n_inputs;
+        switch (a.group) {
+        case 16: *(uint4 *)d = *(const uint4 *)s; break;
+        case 8: *(uint2 *)d = *(const uint2 *)s; break;
+        case 4: *(uint32_t *)d = *(const uint32_t *)s; break;
+        case 2: *(uint16_t *)d = *(const uint16_t *)s; break;
+        default: d[0] = s[0]; break;
+        }
+    }
+}
+
+} // namespace xeng
+
+struct xeng_fengine {
+    xeng_fengine_config cfg{};
+    int group = 1;
+    int32_t *d_coef = nullptr;
+    float2 *d_tw = nullptr, *d_twr = nullptr;
+};
+
+extern "C" {
+
+int xeng_fengine_create(const xeng_fengine_config *cfg, xeng_fengine **out)
+{
+    using namespace xeng;
+    if (!out) return fail(XENG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!cfg) return fail(XENG_EINVAL, "cfg is NULL");
+    if (cfg->n_inputs < 1 || cfg->n_inputs > 65535)
+        return fail(XENG_EINVAL, "n_inputs %d out of [1, 65535]", cfg->n_inputs);
+    if (cfg->n_chans < 1 || cfg->chan0 < 0 || cfg->chan0 + cfg->n_chans > FE_H)
+        return fail(XENG_EINVAL, "channels [%d, %d) outside [0, %d)", cfg->chan0,
+                    cfg->chan0 + cfg->n_chans, FE_H);
+    if (!(cfg->gain > 0.f) || !(cfg->gain < 1e30f))
+        return fail(XENG_EINVAL, "gain must be positive and finite");
+    xeng_fengine *fe = new (std::nothrow) xeng_fengine;
+    if (!fe) return fail(XENG_ENOMEM, "host allocation failed");
+    fe->cfg = *cfg;
+    // inputs per workgroup: the largest power of two up to 16 that divides
+    // the inputs and whose codes fit the LDS set aside for them
+    fe->group = 1;
+    for (int g = FE_MAX_GROUP; g > 1; g >>= 1)
+        if (cfg->n_inputs % g == 0 && g * cfg->n_chans <= FE_CODE_LDS) { fe->group = g; break; }
+
+    // prototype: symmetric Hamming window times a sinc one channel wide,
+    // coded as signed Q1.17 (18-bit) integers
+    const int L = FE_TAPS * FE_P;
+    const double pi = 3.14159265358979323846;
+    std::vector<int32_t> coef(L);
+    for (int l = 0; l < L; ++l) {
+        const double w = 0.54 - 0.46 * std::cos(2.0 * pi * l / (L - 1));
+        const double u = (l - (L - 1) / 2.0) / FE_P;
+        const double s = u == 0.0 ? 1.0 : std::sin(pi * u) / (pi * u);
+        const double c = std::nearbyint(w * s * 131072.0);
+        coef[l] = (int32_t)std::min(131071.0, std::max(-131072.0, c));
+    }
+    std::vector<float2> tw(FE_H), twr(FE_H);
+    for (int k = 0; k < FE_H; ++k) {
+        tw[k] = make_float2((float)std::cos(2.0 * pi * k / FE_H), (float)-std::sin(2.0 * pi * k / FE_H));
+        twr[k] = make_float2((float)std::cos(2.0 * pi * k / FE_P), (float)-std::sin(2.0 * pi * k / FE_P));
+    }
+    hipError_t e = hipMalloc((void **)&fe->d_coef, sizeof(int32_t) * L);
+    if (e == hipSuccess) e = hipMalloc((void **)&fe->d_tw, sizeof(float2) * FE_H);
+    if (e == hipSuccess) e = hipMalloc((void **)&fe->d_twr, sizeof(float2) * FE_H);
+    if (e == hipSuccess) e = hipMemcpy(fe->d_coef, coef.data(), sizeof(int32_t) * L, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(fe->d_tw, tw.data(), sizeof(float2) * FE_H, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(fe->d_twr, twr.data(), sizeof(float2) * FE_H, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (fe->d_coef) (void)hipFree(fe->d_coef);
+        if (fe->d_tw) (void)hipFree(fe->d_tw);
+        if (fe->d_twr) (void)hipFree(fe->d_twr);
+        delete fe;
+        return fail(XENG_ENOMEM, "F-engine tables: %s", hipGetErrorString(e));
+    }
+    *out = fe;
+    return XENG_OK;
+}
+
+int xeng_fengine_group(const xeng_fengine *fe)
+{
+    if (!fe) return fail(XENG_EINVAL, "fe is NULL");
+    return fe->group;
+}
+
+int xeng_fengine_run(xeng_fengine *fe, const int8_t *d_adc, int64_t adc_stride, int64_t n_spectra,
+                     uint8_t *d_out, void *d_spec, void *hip_stream)
+{
+    using namespace xeng;
+    if (!fe || !d_adc || !d_out) return fail(XENG_EINVAL, "NULL argument");
+    if (n_spectra < 1) return fail(XENG_EINVAL, "n_spectra %lld < 1", (long long)n_spectra);
+    const int64_t need = (n_spectra + FE_TAPS - 1) * FE_P;
+    if (adc_stride < need)
+        return fail(XENG_EINVAL, "adc_stride %lld < %lld samples needed for %lld spectra",
+                    (long long)adc_stride, (long long)need, (long long)n_spectra);
+    if (((uintptr_t)d_adc & 7) || (adc_stride & 7))
+        return fail(XENG_EINVAL, "ADC rows must start on 8-byte boundaries");
+    const int G = fe->group;
+    if ((uintptr_t)d_out % G || (d_spec && ((uintptr_t)d_spec & 7)))
+        return fail(XENG_EINVAL, "output misaligned: out needs %d-byte, spec 8-byte alignment", G);
+    const int n_groups = fe->cfg.n_inputs / G;
+    const int64_t blocks = n_spectra * n_groups;
+    if (blocks > 0x7FFFFFFF)
+        return fail(XENG_EINVAL, "n_spectra x input groups %lld above one launch", (long long)blocks);
+    FeArgs a;
+    a.adc = d_adc;
+    a.adc_stride = adc_stride;
+    a.coef = fe->d_coef;
+    a.tw = fe->d_tw;
+    a.tw_r = fe->d_twr;
+    a.out = d_out;
+    a.spec = (float2 *)d_spec;
+    a.n_inputs = fe->cfg.n_inputs;
+    a.n_chans = fe->cfg.n_chans;
+    a.chan0 = fe->cfg.chan0;
+    a.group = G;
+    a.n_groups = n_groups;
+    a.n_blocks = (int32_t)blocks;
+    a.scale = (float)((double)fe->cfg.gain / (131072.0 * FE_P));
+    const size_t lds = (size_t)G * fe->cfg.n_chans;
+    hipLaunchKernelGGL(fengine_kernel, dim3((unsigned)blocks), dim3(FE_THREADS), lds,
+                       (hipStream_t)hip_stream, a);
+    HIP_TRY(hipGetLastError());
+    return XENG_OK;
+}
+
+int xeng_fengine_destroy(xeng_fengine *fe)
+{
+    if (!fe) return XENG_OK;
+    (void)hipDeviceSynchronize();
+    if (fe->d_coef) (void)hipFree(fe->d_coef);
+    if (fe->d_tw) (void)hipFree(fe->d_tw);
+    if (fe->d_twr) (void)hipFree(fe->d_twr);
+    delete fe;
+    return XENG_OK;
+}
+
+} // extern "C"

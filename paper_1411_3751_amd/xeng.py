@@ -29,7 +29,11 @@ EXPORTS = (
     "xeng_set_fast_autos", "xeng_dump_fast_autos",
     "xeng_ingest_create", "xeng_ingest_packet_stride", "xeng_ingest_gulp", "xeng_ingest_stats_get",
     "xeng_ingest_destroy",
+    "xeng_fengine_create", "xeng_fengine_group", "xeng_fengine_run", "xeng_fengine_destroy",
 )
+FENGINE_FFT = 8192
+FENGINE_TAPS = 4
+FENGINE_CHANS = 4096
 PACKET_MAGIC = 0x4C454441
 
 
@@ -47,6 +51,11 @@ class PacketFormat(ctypes.Structure):
 class IngestStats(ctypes.Structure):
     _fields_ = [("received", ctypes.c_int64), ("missing", ctypes.c_int64),
                 ("duplicate", ctypes.c_int64), ("rejected", ctypes.c_int64)]
+
+
+class FEngineConfig(ctypes.Structure):
+    _fields_ = [("n_inputs", ctypes.c_int32), ("chan0", ctypes.c_int32),
+                ("n_chans", ctypes.c_int32), ("gain", ctypes.c_float)]
 
 
 class Subarray(ctypes.Structure):
@@ -116,6 +125,14 @@ def load():
     lib.xeng_ingest_stats_get.restype = i32
     lib.xeng_ingest_destroy.argtypes = [vp]
     lib.xeng_ingest_destroy.restype = i32
+    lib.xeng_fengine_create.argtypes = [ctypes.POINTER(FEngineConfig), ctypes.POINTER(vp)]
+    lib.xeng_fengine_create.restype = i32
+    lib.xeng_fengine_group.argtypes = [vp]
+    lib.xeng_fengine_group.restype = i32
+    lib.xeng_fengine_run.argtypes = [vp, vp, i64, i64, vp, vp, vp]
+    lib.xeng_fengine_run.restype = i32
+    lib.xeng_fengine_destroy.argtypes = [vp]
+    lib.xeng_fengine_destroy.restype = i32
     lib.xeng_set_fast_autos.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32), i32]
     lib.xeng_set_fast_autos.restype = i32
     lib.xeng_dump_fast_autos.argtypes = [vp, pp, i32, i32]
@@ -446,6 +463,60 @@ class Ingest:
         if getattr(self, "_ig", None) and self._ig.value:
             rc = self._lib.xeng_ingest_destroy(self._ig)
             self._ig = ctypes.c_void_p()
+            _check(rc)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FEngine:
+    """GPU F-engine (include/xeng.h): 4-tap, 8192-point Hamming PFB, FFT, one
+    band gain and 4+4-bit requantisation, written as X-engine input."""
+
+    def __init__(self, n_inputs: int, chan0: int, n_chans: int, gain: float):
+        self.cfg = FEngineConfig(int(n_inputs), int(chan0), int(n_chans), float(gain))
+        self._lib = load()
+        self._fe = ctypes.c_void_p()
+        _check(self._lib.xeng_fengine_create(ctypes.byref(self.cfg), ctypes.byref(self._fe)))
+        g = self._lib.xeng_fengine_group(self._fe)
+        if g < 0:
+            _check(g)
+        self.group = g
+
+    def run(self, adc, n_spectra: int, out, spec=None, stream=None):
+        """adc: device int8 [n_inputs][stride] tensor (rows contiguous); out:
+        device uint8 [n_spectra][n_chans][n_inputs]; spec: None or a device
+        complex64 tensor of the same shape for the values before rounding."""
+        N = self.cfg.n_inputs
+        if adc.dim() != 2 or adc.shape[0] != N or adc.element_size() != 1 or not adc.is_cuda \
+                or adc.stride(1) != 1:
+            raise ValueError("adc must be a device int8 [%d][stride] tensor with unit inner stride" % N)
+        shape = (int(n_spectra), self.cfg.n_chans, N)
+        for name, tns, es in (("out", out, 1), ("spec", spec, 8)):
+            if tns is None:
+                continue
+            if tuple(tns.shape) != shape or not tns.is_cuda or not tns.is_contiguous() \
+                    or tns.element_size() != es:
+                raise ValueError("%s must be a contiguous device tensor %s of %d-byte elements"
+                                 % (name, shape, es))
+        _check(self._lib.xeng_fengine_run(
+            self._fe, ctypes.c_void_p(adc.data_ptr()), int(adc.stride(0)), int(n_spectra),
+            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(spec.data_ptr() if spec is not None else 0),
+            ctypes.c_void_p(_stream_handle(stream))))
+
+    def close(self):
+        if getattr(self, "_fe", None) and self._fe.value:
+            rc = self._lib.xeng_fengine_destroy(self._fe)
+            self._fe = ctypes.c_void_p()
             _check(rc)
 
     def __enter__(self):
