@@ -353,8 +353,9 @@ typedef struct xeng_fengine_config {
  * XENG_ENOMEM. */
 int xeng_fengine_create(const xeng_fengine_config *cfg, xeng_fengine **out);
 
-/* Inputs handled by one workgroup (1, 2, 4, 8 or 16; d_out must be aligned
- * to it). Returns it, or XENG_EINVAL (negative) for NULL. */
+/* Inputs handled by one workgroup (1, 2 or 4: the largest that divides
+ * n_inputs; d_out must be aligned to it). Returns it, or XENG_EINVAL
+ * (negative) for NULL. */
 int xeng_fengine_group(const xeng_fengine *fe);
 
 /* Channelise n_spectra spectra of every input, enqueued on hip_stream (a

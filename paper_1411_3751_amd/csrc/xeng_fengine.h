@@ -13,18 +13,20 @@
 //   code  = clip(rint(Re Y), -8, 7) << 4 | clip(rint(Im Y), -8, 7) (nibbles)
 // written to out[m][ch - chan0][n], the X-engine's [time][channel][input].
 //
-// One workgroup of 256 threads takes one spectrum of G consecutive inputs,
-// one input after the other:
-//   * FIR on 16-byte loads of contiguous samples, z[j] = y[2j] + i y[2j+1]
-//     written to LDS;
+// One workgroup of 256 threads takes one spectrum of G <= 4 consecutive
+// inputs, one input after the other; only the FFT buffer lives in LDS (35 KB),
+// and registers stay near 112, so four workgroups share a CU:
+//   * FIR on 16-byte buffer loads of contiguous samples (thread t: positions
+//     [16t, 16t+16) and [4096+16t, 4096+16t+16) of each tap block), exact in
+//     int32; z[j] = y[2j] + i y[2j+1] written to LDS;
 //   * the P-point real FFT as a 4096-point complex FFT of z: three radix-16
-//     Stockham passes, 16 points per thread, exchanged through one padded LDS
-//     buffer (index i at i + i/16 keeps the strided writes conflict-free);
-//     the pass twiddles stay in registers for the whole workgroup;
+//     Stockham passes, 16 points per thread, through one padded LDS buffer
+//     (index i at i + i/16 keeps the strided accesses conflict-free); each
+//     thread's pass twiddles are one 128-byte table row;
 //   * real-FFT split Y[c] = (Z[c] + conj Z[H-c]) / 2 - i exp(-2 pi i c / P)
 //     (Z[c] - conj Z[H-c]) / 2 for the selected channels, requantised;
-//   * the G codes of each channel collect in LDS and leave as one G-byte
-//     store per channel.
+//     thread t keeps the codes of channels t + 256 k in register k, one byte
+//     per input, and stores them as one G-byte word per channel at the end.
 // Workgroups are numbered so that the consecutive ones each XCD runs hold
 // consecutive inputs of one spectrum, so partial output lines meet in that
 // XCD's L2.
@@ -37,14 +39,16 @@ constexpr int FE_H = FE_P / 2;             // complex FFT points
 constexpr int FE_TAPS = 4;
 constexpr int FE_THREADS = 256;            // = FE_H / 16 radix-16 butterflies
 constexpr int FE_LDS = FE_H + FE_H / 16;   // padded complex slots
-constexpr int FE_MAX_GROUP = 16;
-constexpr int FE_CODE_LDS = 30720;         // bytes of LDS for the codes of a group
+constexpr int FE_MAX_GROUP = 4;
+// pass twiddle rows of 16: row t < 256 holds exp(-2 pi i t r / 4096) (pass 3),
+// row 256 + j holds exp(-2 pi i j r / 256) (pass 2), r < 16
+constexpr int FE_TW_ROWS = 256 + 16;
 
 struct FeArgs {
     const int8_t *adc;     // [N][stride] ADC samples
     int64_t adc_stride;
     const int32_t *coef;   // [taps P] 18-bit coefficients
-    const float2 *tw;      // [FE_H] exp(-2 pi i k / FE_H)
+    const float2 *tw;      // [FE_TW_ROWS][16] pass twiddles, rows described at FE_TW_ROWS
     const float2 *tw_r;    // [FE_H] exp(-2 pi i c / FE_P)
     uint8_t *out;          // [n_spectra][n_chans][N]
     float2 *spec;          // optional [n_spectra][n_chans][N] scaled values, or null
@@ -55,6 +59,18 @@ struct FeArgs {
 };
 
 __device__ __forceinline__ int fe_pad(int i) { return i + (i >> 4); }
+
+// the 16 twiddles of row `row`: eight 16-byte loads from one per-thread offset
+__device__ __forceinline__ void fe_twiddle_row(__amdgpu_buffer_rsrc_t rt, int row, float2 (&w)[16])
+{
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        typedef float f32x4 __attribute__((ext_vector_type(4)));
+        const f32x4 q = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rt, row * 128, 16 * p, 0));
+        w[2 * p] = make_float2(q[0], q[1]);
+        w[2 * p + 1] = make_float2(q[2], q[3]);
+    }
+}
 
 __device__ __forceinline__ float2 fe_cmul(float2 a, float2 b)
 {
@@ -129,7 +145,6 @@ __device__ __forceinline__ void fe_dft16(float2 (&v)[16])
 __global__ __launch_bounds__(FE_THREADS) void fengine_kernel(FeArgs a)
 {
     __shared__ float2 z[FE_LDS];
-    extern __shared__ __align__(16) uint8_t fe_codes[];  // [n_chans][group]
     const int t = threadIdx.x;
 
     // workgroup number -> (spectrum, input group); the dispatcher deals
@@ -142,15 +157,20 @@ __global__ __launch_bounds__(FE_THREADS) void fengine_kernel(FeArgs a)
 
     const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
         (void *)a.coef, (short)0, FE_TAPS * FE_P * 4, 0x00020000);
-    // pass-3 twiddles exp(-2 pi i t r / 4096), fixed per thread
-    float2 w3[15];
+    const __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)a.tw, (short)0, FE_TW_ROWS * 128, 0x00020000);
+
+    uint32_t cw[FE_H / FE_THREADS];
 #pragma unroll
-    for (int r = 1; r < 16; ++r) w3[r - 1] = a.tw[t * r];
+    for (int k = 0; k < FE_H / FE_THREADS; ++k) cw[k] = 0;
 
     for (int g = 0; g < a.group; ++g) {
+        // per-thread indices recomputed each input (not held in registers across it)
+        int tt = t;
+        asm volatile("" : "+v"(tt));
         const int n = n0 + g;
         float2 v[16];
-        // FIR on contiguous samples: thread t takes positions [16t, 16t + 16)
+        // FIR on contiguous samples: thread tt takes positions [16t, 16t + 16)
         // and [4096 + 16t, 4096 + 16t + 16) of every tap block, i.e. complex
         // points 8t + e and 2048 + 8t + e (e < 8); 16-byte buffer loads, the
         // next tap's coefficients in flight while this tap accumulates
@@ -162,106 +182,115 @@ __global__ __launch_bounds__(FE_THREADS) void fengine_kernel(FeArgs a)
             for (int tap = 0; tap < FE_TAPS; ++tap)
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    const auto w = __builtin_amdgcn_raw_buffer_load_b128(rx, 16 * t, tap * FE_P + 4096 * h, 0);
+                    const auto w = __builtin_amdgcn_raw_buffer_load_b128(rx, 16 * tt, tap * FE_P + 4096 * h, 0);
 #pragma unroll
                     for (int q = 0; q < 4; ++q) xs[tap][h][q] = w[q];
                 }
             int acc[2][16] = {};
-            uint32_t cb[2][2][16];
-            auto load_coef = [&](int buf, int tap) {
+#pragma unroll
+            for (int tap = 0; tap < FE_TAPS; ++tap) {
+                uint32_t cb[2][16];
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const auto w = __builtin_amdgcn_raw_buffer_load_b128(
-                            rc, 64 * t + 16 * q, 4 * (tap * FE_P + 4096 * h), 0);
+                            rc, 64 * tt + 16 * q, 4 * (tap * FE_P + 4096 * h), 0);
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) cb[buf][h][4 * q + e] = w[e];
+                        for (int e = 0; e < 4; ++e) cb[h][4 * q + e] = w[e];
                     }
-            };
-            load_coef(0, 0);
-#pragma unroll
-            for (int tap = 0; tap < FE_TAPS; ++tap) {
-                if (tap + 1 < FE_TAPS) load_coef((tap + 1) & 1, tap + 1);
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
 #pragma unroll
                     for (int i = 0; i < 16; ++i) {
                         const int xv = (int)(int8_t)(xs[tap][h][i >> 2] >> (8 * (i & 3)));
-                        acc[h][i] += __mul24((int)cb[tap & 1][h][i], xv);
+                        acc[h][i] += __mul24((int)cb[h][i], xv);
                     }
             }
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int e = 0; e < 8; ++e)
-                    z[fe_pad(2048 * h + 8 * t + e)] =
+                    z[fe_pad(2048 * h + 8 * tt + e)] =
                         make_float2((float)acc[h][2 * e], (float)acc[h][2 * e + 1]);
         }
         __syncthreads();
-        // pass 1 (span 1): points t + 256 r, no twiddles; output index 16 t + r
+        // pass 1 (span 1): points tt + 256 r, no twiddles; output index 16 tt + r
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = z[fe_pad(t + 256 * r)];
+        for (int r = 0; r < 16; ++r) v[r] = z[fe_pad(tt + 256 * r)];
         fe_dft16(v);
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 16; ++r) z[fe_pad(16 * t + r)] = v[r];
+        for (int r = 0; r < 16; ++r) z[fe_pad(16 * tt + r)] = v[r];
         __syncthreads();
         // pass 2 (span 16)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = z[fe_pad(t + 256 * r)];
-        // pass-2 twiddles exp(-2 pi i (t%16) r / 256): 256 table entries
+        for (int r = 0; r < 16; ++r) v[r] = z[fe_pad(tt + 256 * r)];
+        // pass-2 twiddles exp(-2 pi i (tt%16) r / 256): 256 table entries
+        {
+            float2 w[16];
+            fe_twiddle_row(rt, 256 + (tt & 15), w);
 #pragma unroll
-        for (int r = 1; r < 16; ++r) v[r] = fe_cmul(v[r], a.tw[(t & 15) * r * 16]);
+            for (int r = 1; r < 16; ++r) v[r] = fe_cmul(v[r], w[r]);
+        }
         fe_dft16(v);
         __syncthreads();
         {
-            const int base = (t >> 4) * 256 + (t & 15);
+            const int base = (tt >> 4) * 256 + (tt & 15);
 #pragma unroll
             for (int r = 0; r < 16; ++r) z[fe_pad(base + 16 * r)] = v[r];
         }
         __syncthreads();
-        // pass 3 (span 256): output in natural order, Z[t + 256 r]
+        // pass 3 (span 256): output in natural order, Z[tt + 256 r]
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = z[fe_pad(t + 256 * r)];
+        for (int r = 0; r < 16; ++r) v[r] = z[fe_pad(tt + 256 * r)];
+        {
+            float2 w[16];
+            fe_twiddle_row(rt, tt, w);
 #pragma unroll
-        for (int r = 1; r < 16; ++r) v[r] = fe_cmul(v[r], w3[r - 1]);
+            for (int r = 1; r < 16; ++r) v[r] = fe_cmul(v[r], w[r]);
+        }
         fe_dft16(v);
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 16; ++r) z[fe_pad(t + 256 * r)] = v[r];
+        for (int r = 0; r < 16; ++r) z[fe_pad(tt + 256 * r)] = v[r];
         __syncthreads();
-        // real-FFT split, gain, requantisation of the selected channels
-        for (int q = t; q < a.n_chans; q += FE_THREADS) {
-            const int c = a.chan0 + q;
-            const float2 zc = z[fe_pad(c)];
-            const float2 zn = z[fe_pad((FE_H - c) & (FE_H - 1))];
-            const float ex = zc.x + zn.x, ey = zc.y - zn.y;        // 2 E
-            const float2 d = make_float2(zc.x - zn.x, zc.y + zn.y); // 2 D
-            const float2 wd = fe_cmul(a.tw_r[c], d);
-            // Y = E - i W D; the halves fold into the scale
-            const float yr = (0.5f * a.scale) * (ex + wd.y);
-            const float yi = (0.5f * a.scale) * (ey - wd.x);
-            if (a.spec)
-                a.spec[((int64_t)m * a.n_chans + q) * a.n_inputs + n] = make_float2(yr, yi);
-            const int qr = (int)fminf(fmaxf(rintf(yr), -8.f), 7.f);
-            const int qi = (int)fminf(fmaxf(rintf(yi), -8.f), 7.f);
-            fe_codes[q * a.group + g] = (uint8_t)(((qr & 15) << 4) | (qi & 15));
+        // real-FFT split, gain, requantisation of the selected channels;
+        // thread tt keeps the codes of channels tt + 256 k in register k
+#pragma unroll
+        for (int k = 0; k < FE_H / FE_THREADS; ++k) {
+            const int q = tt + FE_THREADS * k;
+            if (q < a.n_chans) {
+                const int c = a.chan0 + q;
+                const float2 zc = z[fe_pad(c)];
+                const float2 zn = z[fe_pad((FE_H - c) & (FE_H - 1))];
+                const float ex = zc.x + zn.x, ey = zc.y - zn.y;        // 2 E
+                const float2 d = make_float2(zc.x - zn.x, zc.y + zn.y); // 2 D
+                const float2 wd = fe_cmul(a.tw_r[c], d);
+                // Y = E - i W D; the halves fold into the scale
+                const float yr = (0.5f * a.scale) * (ex + wd.y);
+                const float yi = (0.5f * a.scale) * (ey - wd.x);
+                if (a.spec)
+                    a.spec[((int64_t)m * a.n_chans + q) * a.n_inputs + n] = make_float2(yr, yi);
+                const int qr = (int)fminf(fmaxf(rintf(yr), -8.f), 7.f);
+                const int qi = (int)fminf(fmaxf(rintf(yi), -8.f), 7.f);
+                cw[k] |= (uint32_t)(((qr & 15) << 4) | (qi & 15)) << (8 * g);
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();
     }
 
     // one G-byte store per channel
     uint8_t *o = a.out + (int64_t)m * a.n_chans * a.n_inputs + n0;
-    for (int q = t; q < a.n_chans; q += FE_THREADS) {
-        const uint8_t *s = fe_codes + q * a.group;
-        uint8_t *d = o + (int64_t)q * a.n_inputs;
-        switch (a.group) {
-        case 16: *(uint4 *)d = *(const uint4 *)s; break;
-        case 8: *(uint2 *)d = *(const uint2 *)s; break;
-        case 4: *(uint32_t *)d = *(const uint32_t *)s; break;
-        case 2: *(uint16_t *)d = *(const uint16_t *)s; break;
-        default: d[0] = s[0]; break;
+#pragma unroll
+    for (int k = 0; k < FE_H / FE_THREADS; ++k) {
+        const int q = t + FE_THREADS * k;
+        if (q < a.n_chans) {
+            uint8_t *d = o + (int64_t)q * a.n_inputs;
+            if (a.group == 4) *(uint32_t *)d = cw[k];
+            else if (a.group == 2) *(uint16_t *)d = (uint16_t)cw[k];
+            else d[0] = (uint8_t)cw[k];
         }
     }
 }
@@ -293,11 +322,10 @@ int xeng_fengine_create(const xeng_fengine_config *cfg, xeng_fengine **out)
     xeng_fengine *fe = new (std::nothrow) xeng_fengine;
     if (!fe) return fail(XENG_ENOMEM, "host allocation failed");
     fe->cfg = *cfg;
-    // inputs per workgroup: the largest power of two up to 16 that divides
-    // the inputs and whose codes fit the LDS set aside for them
+    // inputs per workgroup: the largest power of two up to 4 that divides them
     fe->group = 1;
     for (int g = FE_MAX_GROUP; g > 1; g >>= 1)
-        if (cfg->n_inputs % g == 0 && g * cfg->n_chans <= FE_CODE_LDS) { fe->group = g; break; }
+        if (cfg->n_inputs % g == 0) { fe->group = g; break; }
 
     // prototype: symmetric Hamming window times a sinc one channel wide,
     // coded as signed Q1.17 (18-bit) integers
@@ -311,16 +339,20 @@ int xeng_fengine_create(const xeng_fengine_config *cfg, xeng_fengine **out)
         const double c = std::nearbyint(w * s * 131072.0);
         coef[l] = (int32_t)std::min(131071.0, std::max(-131072.0, c));
     }
-    std::vector<float2> tw(FE_H), twr(FE_H);
-    for (int k = 0; k < FE_H; ++k) {
-        tw[k] = make_float2((float)std::cos(2.0 * pi * k / FE_H), (float)-std::sin(2.0 * pi * k / FE_H));
+    std::vector<float2> tw(FE_TW_ROWS * 16), twr(FE_H);
+    for (int row = 0; row < FE_TW_ROWS; ++row)
+        for (int r = 0; r < 16; ++r) {
+            const int k = row < 256 ? (row * r) % FE_H : ((row - 256) * r * 16) % FE_H;
+            tw[row * 16 + r] = make_float2((float)std::cos(2.0 * pi * k / FE_H),
+                                           (float)-std::sin(2.0 * pi * k / FE_H));
+        }
+    for (int k = 0; k < FE_H; ++k)
         twr[k] = make_float2((float)std::cos(2.0 * pi * k / FE_P), (float)-std::sin(2.0 * pi * k / FE_P));
-    }
     hipError_t e = hipMalloc((void **)&fe->d_coef, sizeof(int32_t) * L);
-    if (e == hipSuccess) e = hipMalloc((void **)&fe->d_tw, sizeof(float2) * FE_H);
+    if (e == hipSuccess) e = hipMalloc((void **)&fe->d_tw, sizeof(float2) * tw.size());
     if (e == hipSuccess) e = hipMalloc((void **)&fe->d_twr, sizeof(float2) * FE_H);
     if (e == hipSuccess) e = hipMemcpy(fe->d_coef, coef.data(), sizeof(int32_t) * L, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(fe->d_tw, tw.data(), sizeof(float2) * FE_H, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(fe->d_tw, tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(fe->d_twr, twr.data(), sizeof(float2) * FE_H, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -374,8 +406,7 @@ int xeng_fengine_run(xeng_fengine *fe, const int8_t *d_adc, int64_t adc_stride, 
     a.n_groups = n_groups;
     a.n_blocks = (int32_t)blocks;
     a.scale = (float)((double)fe->cfg.gain / (131072.0 * FE_P));
-    const size_t lds = (size_t)G * fe->cfg.n_chans;
-    hipLaunchKernelGGL(fengine_kernel, dim3((unsigned)blocks), dim3(FE_THREADS), lds,
+    hipLaunchKernelGGL(fengine_kernel, dim3((unsigned)blocks), dim3(FE_THREADS), 0,
                        (hipStream_t)hip_stream, a);
     HIP_TRY(hipGetLastError());
     return XENG_OK;
