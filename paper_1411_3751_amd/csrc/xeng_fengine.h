@@ -40,9 +40,23 @@ constexpr int FE_TAPS = 4;
 constexpr int FE_THREADS = 256;            // = FE_H / 16 radix-16 butterflies
 constexpr int FE_LDS = FE_H + FE_H / 16;   // padded complex slots
 constexpr int FE_MAX_GROUP = 4;
-// pass twiddle rows of 16: row t < 256 holds exp(-2 pi i t r / 4096) (pass 3),
-// row 256 + j holds exp(-2 pi i j r / 256) (pass 2), r < 16
-constexpr int FE_TW_ROWS = 256 + 16;
+// pass twiddle rows of 16 (r < 16): row j < 16 holds exp(-2 pi i j r / 4096),
+// row 16 + i holds exp(-2 pi i i r / 256). Pass 2 of thread t uses row
+// 16 + t%16; pass 3 uses exp(-2 pi i t r / 4096), the product of rows t%16
+// and 16 + t/16.
+constexpr int FE_TW_ROWS = 32;
+constexpr int FE_TW_LDS_ROW = 18;          // LDS row stride in complex values (bank spread)
+
+// exp(-2 pi i k / 32), k < 16: steps between the channels of one thread
+__device__ constexpr float FE_W32[16][2] = {
+    {1.000000000e+00f, 0.f}, {9.807852804e-01f, -1.950903220e-01f},
+    {9.238795325e-01f, -3.826834324e-01f}, {8.314696123e-01f, -5.555702330e-01f},
+    {7.071067812e-01f, -7.071067812e-01f}, {5.555702330e-01f, -8.314696123e-01f},
+    {3.826834324e-01f, -9.238795325e-01f}, {1.950903220e-01f, -9.807852804e-01f},
+    {0.f, -1.000000000e+00f}, {-1.950903220e-01f, -9.807852804e-01f},
+    {-3.826834324e-01f, -9.238795325e-01f}, {-5.555702330e-01f, -8.314696123e-01f},
+    {-7.071067812e-01f, -7.071067812e-01f}, {-8.314696123e-01f, -5.555702330e-01f},
+    {-9.238795325e-01f, -3.826834324e-01f}, {-9.807852804e-01f, -1.950903220e-01f}};
 
 struct FeArgs {
     const int8_t *adc;     // [N][stride] ADC samples
@@ -60,15 +74,15 @@ struct FeArgs {
 
 __device__ __forceinline__ int fe_pad(int i) { return i + (i >> 4); }
 
-// the 16 twiddles of row `row`: eight 16-byte loads from one per-thread offset
-__device__ __forceinline__ void fe_twiddle_row(__amdgpu_buffer_rsrc_t rt, int row, float2 (&w)[16])
+// the 16 twiddles of LDS row `row`
+__device__ __forceinline__ void fe_twiddle_row(const float2 *twl, int row, float2 (&w)[16])
 {
+    const float4 *p = (const float4 *)(twl + row * FE_TW_LDS_ROW);
 #pragma unroll
-    for (int p = 0; p < 8; ++p) {
-        typedef float f32x4 __attribute__((ext_vector_type(4)));
-        const f32x4 q = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rt, row * 128, 16 * p, 0));
-        w[2 * p] = make_float2(q[0], q[1]);
-        w[2 * p + 1] = make_float2(q[2], q[3]);
+    for (int k = 0; k < 8; ++k) {
+        const float4 q = p[k];
+        w[2 * k] = make_float2(q.x, q.y);
+        w[2 * k + 1] = make_float2(q.z, q.w);
     }
 }
 
@@ -145,6 +159,7 @@ __device__ __forceinline__ void fe_dft16(float2 (&v)[16])
 __global__ __launch_bounds__(FE_THREADS) void fengine_kernel(FeArgs a)
 {
     __shared__ float2 z[FE_LDS];
+    __shared__ __align__(16) float2 twl[FE_TW_ROWS * FE_TW_LDS_ROW];
     const int t = threadIdx.x;
 
     // workgroup number -> (spectrum, input group); the dispatcher deals
@@ -157,12 +172,17 @@ __global__ __launch_bounds__(FE_THREADS) void fengine_kernel(FeArgs a)
 
     const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
         (void *)a.coef, (short)0, FE_TAPS * FE_P * 4, 0x00020000);
-    const __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)a.tw, (short)0, FE_TW_ROWS * 128, 0x00020000);
+    // pass twiddle table into LDS (32 rows of 16, padded rows)
+    for (int i = t; i < FE_TW_ROWS * 16; i += FE_THREADS)
+        twl[(i >> 4) * FE_TW_LDS_ROW + (i & 15)] = a.tw[i];
+    // this thread's first channel twiddle exp(-2 pi i (chan0 + t) / P); the
+    // others follow by steps of exp(-2 pi i 256 / P) = exp(-2 pi i / 32)
+    const float2 wc0 = a.tw_r[(a.chan0 + t) & (FE_H - 1)];
 
     uint32_t cw[FE_H / FE_THREADS];
 #pragma unroll
     for (int k = 0; k < FE_H / FE_THREADS; ++k) cw[k] = 0;
+    __syncthreads();
 
     for (int g = 0; g < a.group; ++g) {
         // per-thread indices recomputed each input (not held in registers across it)
@@ -170,49 +190,68 @@ __global__ __launch_bounds__(FE_THREADS) void fengine_kernel(FeArgs a)
         asm volatile("" : "+v"(tt));
         const int n = n0 + g;
         float2 v[16];
-        // FIR on contiguous samples: thread tt takes positions [16t, 16t + 16)
-        // and [4096 + 16t, 4096 + 16t + 16) of every tap block, i.e. complex
-        // points 8t + e and 2048 + 8t + e (e < 8); 16-byte buffer loads, the
-        // next tap's coefficients in flight while this tap accumulates
-        const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(a.adc + (int64_t)n * a.adc_stride + m * FE_P), (short)0, FE_TAPS * FE_P, 0x00020000);
+        // FIR. Thread tt takes positions A = [16 tt, 16 tt + 16) and their
+        // mirror A' = [P - 16 tt - 16, P - 16 tt) of every tap block (complex
+        // points 8 tt + e and H - 8 tt - 8 + e, e < 8). The prototype is
+        // symmetric, c[l] = c[4P - 1 - l], so taps 2 and 3 at a position are
+        // taps 1 and 0 at its mirror: loading taps 0 and 1 over A and A' gives
+        // all four.
         {
+            const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(a.adc + (int64_t)n * a.adc_stride + m * FE_P), (short)0, FE_TAPS * FE_P, 0x00020000);
+            const int oa = 16 * tt, ob = FE_P - 16 * tt - 16;
             uint32_t xs[FE_TAPS][2][4];
 #pragma unroll
             for (int tap = 0; tap < FE_TAPS; ++tap)
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    const auto w = __builtin_amdgcn_raw_buffer_load_b128(rx, 16 * tt, tap * FE_P + 4096 * h, 0);
+                    const auto w = __builtin_amdgcn_raw_buffer_load_b128(rx, h ? ob : oa, tap * FE_P, 0);
 #pragma unroll
                     for (int q = 0; q < 4; ++q) xs[tap][h][q] = w[q];
                 }
-            int acc[2][16] = {};
+            // Two halves, each needing 32 coefficients: half s takes A positions
+            // [8s, 8s+8) and A' positions [8(1-s), 8(1-s)+8), whose mirrors are
+            // each other's. cA = taps 0, 1 at A + 8s; cB = taps 0, 1 at A' + 8(1-s).
+            auto xb = [&](int tap, int h, int i) { return (int)(int8_t)(xs[tap][h][i >> 2] >> (8 * (i & 3))); };
 #pragma unroll
-            for (int tap = 0; tap < FE_TAPS; ++tap) {
-                uint32_t cb[2][16];
+            for (int hs = 0; hs < 2; ++hs) {
+                const int sa = 8 * hs, sb = 8 - 8 * hs;
+                uint32_t cA[2][8], cB[2][8];
 #pragma unroll
-                for (int h = 0; h < 2; ++h)
+                for (int tap = 0; tap < 2; ++tap)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const auto w = __builtin_amdgcn_raw_buffer_load_b128(
-                            rc, 64 * tt + 16 * q, 4 * (tap * FE_P + 4096 * h), 0);
+                    for (int q = 0; q < 2; ++q) {
+                        const auto wa = __builtin_amdgcn_raw_buffer_load_b128(rc, 4 * (oa + sa) + 16 * q,
+                                                                              4 * FE_P * tap, 0);
+                        const auto wb = __builtin_amdgcn_raw_buffer_load_b128(rc, 4 * (ob + sb) + 16 * q,
+                                                                              4 * FE_P * tap, 0);
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) cb[h][4 * q + e] = w[e];
+                        for (int e = 0; e < 4; ++e) {
+                            cA[tap][4 * q + e] = wa[e];
+                            cB[tap][4 * q + e] = wb[e];
+                        }
                     }
+                int acc[2][8];
 #pragma unroll
-                for (int h = 0; h < 2; ++h)
+                for (int j = 0; j < 8; ++j) {
+                    // A position i = sa + j; its mirror 15 - i = sb + 7 - j in A'
+                    const int i = sa + j;
+                    acc[0][j] = __mul24((int)cA[0][j], xb(0, 0, i)) + __mul24((int)cA[1][j], xb(1, 0, i)) +
+                                __mul24((int)cB[1][7 - j], xb(2, 0, i)) + __mul24((int)cB[0][7 - j], xb(3, 0, i));
+                    // A' position i' = sb + j; its mirror 15 - i' = sa + 7 - j in A
+                    const int ib = sb + j;
+                    acc[1][j] = __mul24((int)cB[0][j], xb(0, 1, ib)) + __mul24((int)cB[1][j], xb(1, 1, ib)) +
+                                 __mul24((int)cA[1][7 - j], xb(2, 1, ib)) + __mul24((int)cA[0][7 - j], xb(3, 1, ib));
+                }
+                // complex points 8 tt + sa/2 + e and H - 8 tt - 8 + sb/2 + e, e < 4
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        const int xv = (int)(int8_t)(xs[tap][h][i >> 2] >> (8 * (i & 3)));
-                        acc[h][i] += __mul24((int)cb[h][i], xv);
-                    }
+                for (int e = 0; e < 4; ++e) {
+                    z[fe_pad(8 * tt + sa / 2 + e)] = make_float2((float)acc[0][2 * e], (float)acc[0][2 * e + 1]);
+                    z[fe_pad(FE_H - 8 * tt - 8 + sb / 2 + e)] =
+                        make_float2((float)acc[1][2 * e], (float)acc[1][2 * e + 1]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int e = 0; e < 8; ++e)
-                    z[fe_pad(2048 * h + 8 * tt + e)] =
-                        make_float2((float)acc[h][2 * e], (float)acc[h][2 * e + 1]);
         }
         __syncthreads();
         // pass 1 (span 1): points tt + 256 r, no twiddles; output index 16 tt + r
@@ -223,13 +262,12 @@ __global__ __launch_bounds__(FE_THREADS) void fengine_kernel(FeArgs a)
 #pragma unroll
         for (int r = 0; r < 16; ++r) z[fe_pad(16 * tt + r)] = v[r];
         __syncthreads();
-        // pass 2 (span 16)
+        // pass 2 (span 16), twiddles exp(-2 pi i (tt%16) r / 256)
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = z[fe_pad(tt + 256 * r)];
-        // pass-2 twiddles exp(-2 pi i (tt%16) r / 256): 256 table entries
         {
             float2 w[16];
-            fe_twiddle_row(rt, 256 + (tt & 15), w);
+            fe_twiddle_row(twl, 16 + (tt & 15), w);
 #pragma unroll
             for (int r = 1; r < 16; ++r) v[r] = fe_cmul(v[r], w[r]);
         }
@@ -241,12 +279,17 @@ __global__ __launch_bounds__(FE_THREADS) void fengine_kernel(FeArgs a)
             for (int r = 0; r < 16; ++r) z[fe_pad(base + 16 * r)] = v[r];
         }
         __syncthreads();
-        // pass 3 (span 256): output in natural order, Z[tt + 256 r]
+        // pass 3 (span 256), twiddles exp(-2 pi i tt r / 4096); output in
+        // natural order, Z[tt + 256 r]
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = z[fe_pad(tt + 256 * r)];
         {
+            // exp(-2 pi i tt r / 4096) = row tt%16 times row 16 + tt/16, applied in turn
             float2 w[16];
-            fe_twiddle_row(rt, tt, w);
+            fe_twiddle_row(twl, tt & 15, w);
+#pragma unroll
+            for (int r = 1; r < 16; ++r) v[r] = fe_cmul(v[r], w[r]);
+            fe_twiddle_row(twl, 16 + (tt >> 4), w);
 #pragma unroll
             for (int r = 1; r < 16; ++r) v[r] = fe_cmul(v[r], w[r]);
         }
@@ -256,27 +299,36 @@ __global__ __launch_bounds__(FE_THREADS) void fengine_kernel(FeArgs a)
         for (int r = 0; r < 16; ++r) z[fe_pad(tt + 256 * r)] = v[r];
         __syncthreads();
         // real-FFT split, gain, requantisation of the selected channels;
-        // thread tt keeps the codes of channels tt + 256 k in register k
+        // thread tt keeps the codes of channels c0 + 256 k in register k.
+        {
+            const int c0 = a.chan0 + tt;
+            // z index of channel c0 + 256 k is pad(c0) + 272 k; of H - c0 - 256 k
+            // it is pad(H - c0) - 272 k (channel 0 pairs with itself)
+            const int pc0 = fe_pad(c0), pn0 = fe_pad(FE_H - c0);
+            // the channel twiddles are rebuilt from wc0 for every input rather
+            // than held in sixteen register pairs across the loop
+            float2 wc = wc0;
+            asm volatile("" : "+v"(wc.x), "+v"(wc.y));
 #pragma unroll
-        for (int k = 0; k < FE_H / FE_THREADS; ++k) {
-            const int q = tt + FE_THREADS * k;
-            if (q < a.n_chans) {
-                const int c = a.chan0 + q;
-                const float2 zc = z[fe_pad(c)];
-                const float2 zn = z[fe_pad((FE_H - c) & (FE_H - 1))];
-                const float ex = zc.x + zn.x, ey = zc.y - zn.y;        // 2 E
-                const float2 d = make_float2(zc.x - zn.x, zc.y + zn.y); // 2 D
-                const float2 wd = fe_cmul(a.tw_r[c], d);
-                // Y = E - i W D; the halves fold into the scale
-                const float yr = (0.5f * a.scale) * (ex + wd.y);
-                const float yi = (0.5f * a.scale) * (ey - wd.x);
-                if (a.spec)
-                    a.spec[((int64_t)m * a.n_chans + q) * a.n_inputs + n] = make_float2(yr, yi);
-                const int qr = (int)fminf(fmaxf(rintf(yr), -8.f), 7.f);
-                const int qi = (int)fminf(fmaxf(rintf(yi), -8.f), 7.f);
-                cw[k] |= (uint32_t)(((qr & 15) << 4) | (qi & 15)) << (8 * g);
+            for (int k = 0; k < FE_H / FE_THREADS; ++k) {
+                const int q = tt + FE_THREADS * k;
+                if (q < a.n_chans) {
+                    const float2 zc = z[pc0 + 272 * k];
+                    const float2 zn = z[(k == 0 && c0 == 0) ? 0 : pn0 - 272 * k];
+                    const float ex = zc.x + zn.x, ey = zc.y - zn.y;        // 2 E
+                    const float2 d = make_float2(zc.x - zn.x, zc.y + zn.y); // 2 D
+                    const float2 wk = k ? fe_cmul(wc, make_float2(FE_W32[k][0], FE_W32[k][1])) : wc;
+                    const float2 wd = fe_cmul(wk, d);
+                    // Y = E - i W D; the halves fold into the scale
+                    const float yr = (0.5f * a.scale) * (ex + wd.y);
+                    const float yi = (0.5f * a.scale) * (ey - wd.x);
+                    if (a.spec)
+                        a.spec[((int64_t)m * a.n_chans + q) * a.n_inputs + n] = make_float2(yr, yi);
+                    const int qr = (int)fminf(fmaxf(rintf(yr), -8.f), 7.f);
+                    const int qi = (int)fminf(fmaxf(rintf(yi), -8.f), 7.f);
+                    cw[k] |= (uint32_t)(((qr & 15) << 4) | (qi & 15)) << (8 * g);
+                }
             }
-            __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();
     }
@@ -342,7 +394,7 @@ int xeng_fengine_create(const xeng_fengine_config *cfg, xeng_fengine **out)
     std::vector<float2> tw(FE_TW_ROWS * 16), twr(FE_H);
     for (int row = 0; row < FE_TW_ROWS; ++row)
         for (int r = 0; r < 16; ++r) {
-            const int k = row < 256 ? (row * r) % FE_H : ((row - 256) * r * 16) % FE_H;
+            const int k = row < 16 ? (row * r) % FE_H : ((row - 16) * r * 16) % FE_H;
             tw[row * 16 + r] = make_float2((float)std::cos(2.0 * pi * k / FE_H),
                                            (float)-std::sin(2.0 * pi * k / FE_H));
         }
