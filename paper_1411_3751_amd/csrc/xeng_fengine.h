@@ -14,19 +14,21 @@
 // written to out[m][ch - chan0][n], the X-engine's [time][channel][input].
 //
 // One workgroup of 256 threads takes one spectrum of G <= 4 consecutive
-// inputs, one input after the other; only the FFT buffer lives in LDS (35 KB),
-// and registers stay near 112, so four workgroups share a CU:
-//   * FIR on 16-byte buffer loads of contiguous samples (thread t: positions
-//     [16t, 16t+16) and [4096+16t, 4096+16t+16) of each tap block), exact in
-//     int32; z[j] = y[2j] + i y[2j+1] written to LDS;
+// inputs, one input after the other; LDS holds the FFT buffer (35 KB) and the
+// pass-twiddle tables (4.6 KB), registers stay under 128, so four workgroups
+// share a CU:
+//   * FIR, exact in int32: thread t owns samples [16t, 16t+16) and their
+//     mirror [P-16t-16, P-16t) of each tap block. The prototype is
+//     symmetric (c[l] = c[4P-1-l]), so taps 2 and 3 at a position are taps
+//     1 and 0 at its mirror: only taps 0 and 1 are loaded. z[j] = y[2j] +
+//     i y[2j+1] goes to LDS;
 //   * the P-point real FFT as a 4096-point complex FFT of z: three radix-16
 //     Stockham passes, 16 points per thread, through one padded LDS buffer
-//     (index i at i + i/16 keeps the strided accesses conflict-free); each
-//     thread's pass twiddles are one 128-byte table row;
+//     (index i at i + i/16 keeps the strided accesses conflict-free);
 //   * real-FFT split Y[c] = (Z[c] + conj Z[H-c]) / 2 - i exp(-2 pi i c / P)
 //     (Z[c] - conj Z[H-c]) / 2 for the selected channels, requantised;
-//     thread t keeps the codes of channels t + 256 k in register k, one byte
-//     per input, and stores them as one G-byte word per channel at the end.
+//     thread t keeps the codes of channels chan0 + t + 256 k in register k,
+//     one byte per input, and stores them as one G-byte word per channel.
 // Workgroups are numbered so that the consecutive ones each XCD runs hold
 // consecutive inputs of one spectrum, so partial output lines meet in that
 // XCD's L2.
