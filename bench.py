@@ -412,6 +412,69 @@ def fengine_bench(args):
     print(json.dumps(res), flush=True)
 
 
+def fx_bench(args):
+    """The whole FX correlator on one GPU: per 8192-sample gulp, the F-engine
+    channelises 512 ADC inputs (64 spectra per launch, channels 1250..3647)
+    straight into the gulp buffer, then the X-engine integrates the gulp.
+    The ADC block of one launch is reused for every launch (contents do not
+    change the work). Reports ms per gulp and the real-time factor."""
+    import torch
+
+    import synth
+    from paper_1411_3751_amd import Correlator, FEngine
+
+    torch.cuda.set_device(0)
+    c = FENGINE_CFG
+    N, M, F, T = c["n_inputs"], c["n_spectra"], c["n_chans"], 8192
+    S = FE_P * (M + FE_TAPS - 1)
+    log("generating %d x %d ADC samples on the device ..." % (N, S))
+    d_adc = synth.adc_device(c["seed"], N, S, "cuda")
+    gulp = torch.empty((T, F, N), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    fe = FEngine(N, c["chan0"], F, c["gain"])
+    xc = Correlator([dict(n_inputs=N, n_chans=F, n_time=T, in_bits=4)], stream=stream)
+
+    def one_gulp():
+        for m0 in range(0, T, M):
+            fe.run(d_adc, M, gulp[m0:m0 + M], stream=stream)
+        xc.correlate([gulp])
+
+    for _ in range(max(1, args.warmup)):
+        one_gulp()
+    xc.reset()
+    torch.cuda.synchronize()
+    n = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(n)]
+    for g in range(n):
+        ev[g][0].record(stream)
+        for m0 in range(0, T, M):
+            fe.run(d_adc, M, gulp[m0:m0 + M], stream=stream)
+        ev[g][1].record(stream)
+        xc.correlate([gulp])
+        ev[g][2].record(stream)
+    torch.cuda.synchronize()
+    ms = ev[0][0].elapsed_time(ev[-1][2]) / n
+    ms_f = sum(a.elapsed_time(b) for a, b, _ in ev) / n
+    ms_x = sum(b.elapsed_time(c) for _, b, c in ev) / n
+    out = xc.dump()[0]
+    torch.cuda.synchronize()
+    xc.close()
+    fe.close()
+    gulp_s = T / CHANNEL_HZ
+    tri = N * (N + 1) // 2
+    res = {"metric": "end-to-end FX correlator real-time factor at N=512 (F-engine + X-engine per gulp)",
+           "value": round(gulp_s / (ms * 1e-3), 2), "unit": "x real time", "n_gpus": 1, "steps": n,
+           "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32+int8", "data": "synthetic",
+           "config": {"workload": "fx_512", "n_inputs": N, "n_chans": F, "n_time": T,
+                      "chan0": c["chan0"], "fft": FE_P, "taps": FE_TAPS, "gain": c["gain"]},
+           "ms_fengine": round(ms_f, 3), "ms_xengine": round(ms_x, 3),
+           "fengine_gsamples_per_s": round(N * T * FE_P / (ms_f * 1e-3) / 1e9, 1),
+           "xengine_tops": round(F * tri * T * OPS_PER_CMAC / (ms_x * 1e-3) / 1e12, 1),
+           "dump_shape": list(out.shape)}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -437,11 +500,19 @@ def main():
                     help="time the packet ingest (corner turn of F-engine packets) instead")
     ap.add_argument("--fengine", action="store_true",
                     help="time the F-engine (PFB + FFT + 4+4-bit requantisation) instead")
+    ap.add_argument("--fx", action="store_true",
+                    help="time F-engine + X-engine per 8192-sample gulp (512 inputs, 2398 channels)")
     ap.add_argument("--stream-gulps", type=int, default=260)
     ap.add_argument("--dump-every", type=int, default=26)
     ap.add_argument("--pace", type=float, default=4.0,
                     help="latency run: gulps arrive at this multiple of the real-time rate")
     args = ap.parse_args()
+    if args.fx:
+        if args.gpus != 1:
+            print("bench.py measures one GPU (--gpus %d requested)" % args.gpus, file=sys.stderr)
+            sys.exit(2)
+        fx_bench(args)
+        return
     if args.fengine:
         if args.gpus != 1:
             print("bench.py measures one GPU (--gpus %d requested)" % args.gpus, file=sys.stderr)
