@@ -158,7 +158,7 @@ __device__ __forceinline__ void fe_dft16(float2 (&v)[16])
     for (int k = 0; k < 16; ++k) v[k] = t[k];
 }
 
-__global__ __launch_bounds__(FE_THREADS) void fengine_kernel(FeArgs a)
+__global__ __launch_bounds__(FE_THREADS, 4) void fengine_kernel(FeArgs a)
 {
     __shared__ float2 z[FE_LDS];
     __shared__ __align__(16) float2 twl[FE_TW_ROWS * FE_TW_LDS_ROW];
@@ -179,7 +179,9 @@ __global__ __launch_bounds__(FE_THREADS) void fengine_kernel(FeArgs a)
         twl[(i >> 4) * FE_TW_LDS_ROW + (i & 15)] = a.tw[i];
     // this thread's first channel twiddle exp(-2 pi i (chan0 + t) / P); the
     // others follow by steps of exp(-2 pi i 256 / P) = exp(-2 pi i / 32)
-    const float2 wc0 = a.tw_r[(a.chan0 + t) & (FE_H - 1)];
+    const float hs = 0.5f * a.scale;
+    const float2 wr0 = a.tw_r[(a.chan0 + t) & (FE_H - 1)];
+    const float2 wc0 = make_float2(hs * wr0.x, hs * wr0.y);
 
     uint32_t cw[FE_H / FE_THREADS];
 #pragma unroll
@@ -307,8 +309,8 @@ __global__ __launch_bounds__(FE_THREADS) void fengine_kernel(FeArgs a)
             // z index of channel c0 + 256 k is pad(c0) + 272 k; of H - c0 - 256 k
             // it is pad(H - c0) - 272 k (channel 0 pairs with itself)
             const int pc0 = fe_pad(c0), pn0 = fe_pad(FE_H - c0);
-            // the channel twiddles are rebuilt from wc0 for every input rather
-            // than held in sixteen register pairs across the loop
+            // the channel twiddles (already times the scale) are rebuilt from
+            // wc0 for every input rather than held in sixteen register pairs
             float2 wc = wc0;
             asm volatile("" : "+v"(wc.x), "+v"(wc.y));
 #pragma unroll
@@ -321,14 +323,21 @@ __global__ __launch_bounds__(FE_THREADS) void fengine_kernel(FeArgs a)
                     const float2 d = make_float2(zc.x - zn.x, zc.y + zn.y); // 2 D
                     const float2 wk = k ? fe_cmul(wc, make_float2(FE_W32[k][0], FE_W32[k][1])) : wc;
                     const float2 wd = fe_cmul(wk, d);
-                    // Y = E - i W D; the halves fold into the scale
-                    const float yr = (0.5f * a.scale) * (ex + wd.y);
-                    const float yi = (0.5f * a.scale) * (ey - wd.x);
+                    // Y = s (E - i W D) with s = scale / 2 (the halves of E and D)
+                    const float yr = __builtin_fmaf(hs, ex, wd.y);
+                    const float yi = __builtin_fmaf(hs, ey, -wd.x);
                     if (a.spec)
                         a.spec[((int64_t)m * a.n_chans + q) * a.n_inputs + n] = make_float2(yr, yi);
-                    const int qr = (int)fminf(fmaxf(rintf(yr), -8.f), 7.f);
-                    const int qi = (int)fminf(fmaxf(rintf(yi), -8.f), 7.f);
-                    cw[k] |= (uint32_t)(((qr & 15) << 4) | (qi & 15)) << (8 * g);
+                    // round half to even and clip to [-8, 7]: adding 1.5 * 2^23
+                    // leaves round(y) in the low mantissa bits (|y| < 2^22), the
+                    // clip is an integer clamp on those bits, whose low nibble
+                    // is then the two's complement code
+                    constexpr int MAGIC = 0x4B400000;
+                    const int br = __builtin_bit_cast(int, yr + 12582912.0f);
+                    const int bi = __builtin_bit_cast(int, yi + 12582912.0f);
+                    const uint32_t qr = (uint32_t)min(max(br, MAGIC - 8), MAGIC + 7);
+                    const uint32_t qi = (uint32_t)min(max(bi, MAGIC - 8), MAGIC + 7);
+                    cw[k] |= (((qr << 4) & 0xF0u) | (qi & 15u)) << (8 * g);
                 }
             }
         }
