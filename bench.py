@@ -205,6 +205,55 @@ def stream_bench(args):
         "ingest_gulp_ms_p50": float(np.percentile(arr, 50)),
         "ingest_gulp_ms_p99": float(np.percentile(arr, 99)),
     })
+    # 4. H2D-inclusive: gulps replayed from a pool of pinned host buffers by
+    # hipMemcpyAsync on the ring's ingest stream (PCIe in the loop)
+    if args.stream_h2d_gulps > 0:
+        import ctypes
+        hip = ctypes.CDLL("libamdhip64.so")
+        vp, sz = ctypes.c_void_p, ctypes.c_size_t
+        hip.hipHostMalloc.argtypes = [ctypes.POINTER(vp), sz, ctypes.c_uint]
+        hip.hipHostFree.argtypes = [vp]
+        hip.hipMemcpy.argtypes = [vp, vp, sz, ctypes.c_int]
+        hip.hipMemcpyAsync.argtypes = [vp, vp, sz, ctypes.c_int, vp]
+        nbytes = F * N * T
+        pool = []
+        for g in range(2):
+            p_ = vp()
+            if hip.hipHostMalloc(ctypes.byref(p_), nbytes, 0) != 0:
+                raise RuntimeError("hipHostMalloc of %d bytes failed" % nbytes)
+            pool.append(p_)
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        for g, p_ in enumerate(pool):
+            gen.fill(scratch.data_ptr(), g * T, T, torch.cuda.current_stream().cuda_stream)
+            torch.cuda.synchronize()
+            if hip.hipMemcpy(p_, scratch.data_ptr(), nbytes, 2) != 0:
+                raise RuntimeError("hipMemcpy D2H failed")
+        del scratch
+        torch.cuda.empty_cache()
+        nh = args.stream_h2d_gulps
+
+        def feed_h2d(st, g0, cnt):
+            for g in range(g0, g0 + cnt):
+                ptr, ist = st.next_slot()
+                if hip.hipMemcpyAsync(ptr, pool[g % 2], nbytes, 1, ist) != 0:
+                    raise RuntimeError("hipMemcpyAsync H2D failed")
+                st.push()
+
+        with Stream(sub, n_slots=slots, dump_every=every, host_dumps=hd) as st:
+            feed_h2d(st, 0, slots)
+            st.gulp_times(slots - 1)
+            t0 = time.perf_counter()
+            feed_h2d(st, slots, nh)
+            st.gulp_times(slots + nh - 1)
+            wall = time.perf_counter() - t0
+        for p_ in pool:
+            hip.hipHostFree(p_)
+        res["rtf_h2d"] = nh * gulp_s / wall
+        res["h2d_gbs"] = nh * nbytes / wall / 1e9
+        res["gulps_timed_h2d"] = nh
+        log("stream: H2D-inclusive %d gulps in %.2f s: RTF %.2f, %.1f GB/s" % (
+            nh, wall, res["rtf_h2d"], res["h2d_gbs"]))
+
     out = {
         "metric": METRIC, "value": round(res["sustained_tops"], 2), "unit": "Tops/s",
         "n_gpus": 1, "steps": n, "warmup": 2 * slots, "ms_per_step": round(1e3 * gulp_s / res["rtf"], 3),
@@ -482,9 +531,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--workload", default="leda_gulp",
-                    choices=["leda_gulp", "fp8_variant", "int8_variant"],
-                    help="input shape (the default is the headline configuration; the others "
-                         "time the precision variants)")
+                    choices=["leda_gulp", "fp8_variant", "int8_variant", "tiny", "n64"],
+                    help="input shape (the default is the headline configuration; fp8_variant and "
+                         "int8_variant time the precision variants; tiny (N=32) and n64 (N=64, "
+                         "512 channels, 4096 samples) the small-N, memory-bound regime)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library time its kernel and schedule choices on the input first")
     ap.add_argument("--engine", default=None, choices=["i8", "fp8"],
                     help="arithmetic engine (default: fp8 for fp8_variant, else i8)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -503,6 +555,9 @@ def main():
     ap.add_argument("--fx", action="store_true",
                     help="time F-engine + X-engine per 8192-sample gulp (512 inputs, 2398 channels)")
     ap.add_argument("--stream-gulps", type=int, default=260)
+    ap.add_argument("--stream-h2d-gulps", type=int, default=12,
+                    help="stream mode: gulps timed with the input copied from pinned host memory "
+                         "(0 skips that phase)")
     ap.add_argument("--dump-every", type=int, default=26)
     ap.add_argument("--pace", type=float, default=4.0,
                     help="latency run: gulps arrive at this multiple of the real-time rate")
@@ -572,6 +627,8 @@ def main():
 
     corr = Correlator([dict(n_inputs=N, n_chans=F, n_time=T, in_bits=in_bits,
                             engine=1 if engine == "fp8" else 0)], stream=stream)
+    if args.autotune:
+        corr.autotune([d_samples])
     log("plan:", json.dumps(corr.plan()))
 
     def step():
@@ -622,10 +679,12 @@ def main():
         "dtype": "fp8_e4m3" if engine == "fp8" else "int8",
         "data": "synthetic",
         "config": {"workload": name, "n_inputs": N, "n_chans": F, "n_time": T,
-                   "in_bits": in_bits, "engine": engine},
+                   "in_bits": in_bits, "engine": engine, "autotuned": bool(args.autotune)},
         "cmac_per_s": cmac_per_step / (ms_step * 1e-3),
         "pct_int8_peak": round(100.0 * value / peak, 2),
         "rtf_gulp": round(stream_s / (ms_step * 1e-3), 1),
+        # minimum HBM bytes of a step: the samples once plus the visibilities once
+        "hbm_gbs_algorithmic": round((N * F * T * (in_bits // 4) + F * tri * 8) / (ms_step * 1e-3) / 1e9, 1),
         "ms_kernel": round(ms_kernel, 4),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),

@@ -165,6 +165,8 @@ WORKLOADS = {
     "int8_variant": dict(n_inputs=512, n_chans=256, n_time=16384, sigma=20.0, in_bits=8, tone=False, k=2),
     # subarray s of the batch takes (n_inputs, n_chans) = BATCH_SHAPES[s]
     "batch": dict(n_inputs=None, n_chans=None, n_time=4096, sigma=2.5, in_bits=4, tone=False, k=3),
+    # the batch's first subarray on its own (same seed): the small-N, memory-bound shape
+    "n64": dict(n_inputs=64, n_chans=512, n_time=4096, sigma=2.5, in_bits=4, tone=False, k=3),
 }
 # Batched subarrays of uneven size: (N, F) with equal input bytes per call for N >= 256.
 BATCH_SHAPES = [(64, 512), (256, 256), (512, 128), (1024, 64), (2048, 32)]
