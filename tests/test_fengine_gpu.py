@@ -137,6 +137,31 @@ def test_fengine_full_size_sampled(torch_cuda):
     check(codes, Y, ref_codes, ref_Y, tol)
 
 
+def test_fengine_maximum_inputs(torch_cuda):
+    """The largest input count the boundary takes (65535, odd: one input per
+    workgroup), one spectrum, sampled inputs against the reference."""
+    torch = torch_cuda
+    from paper_1411_3751_amd import FEngine
+    N, M, chan0, F = 65535, 1, 1392, 24
+    print("case fengine max inputs N=%d" % N, flush=True)
+    d_adc = synth.adc_device(9, N, P * TAPS, "cuda")
+    rows = [0, 1, 4097, 32767, 65533, 65534]
+    host_rows = d_adc[rows].cpu().numpy()
+    gain = fe.gain_for_rms(host_rows, 2.5, 1250, 2398, n_spectra=1)
+    out = torch.empty((M, F, N), dtype=torch.uint8, device="cuda")
+    spec = torch.empty((M, F, N), dtype=torch.complex64, device="cuda")
+    with FEngine(N, chan0, F, gain) as f:
+        assert f.group == 1
+        f.run(d_adc, M, out, spec)
+        torch.cuda.synchronize()
+    codes = out.cpu().numpy()[:, :, rows]
+    Y = spec.cpu().numpy()[:, :, rows]
+    ref_codes, ref_Y = fe.fengine(host_rows, M, gain, chan0, F)
+    tol = np.array([[tolerance(host_rows[a], 0, gain) for a in range(len(rows))]])
+    check(codes, Y, ref_codes, ref_Y, tol)
+    del d_adc
+
+
 def test_fengine_feeds_xengine(torch_cuda):
     """F-engine output straight into the X-engine; against the reference
     F-engine's codes correlated by the reference X-engine."""
