@@ -524,6 +524,65 @@ def fx_bench(args):
     print(json.dumps(res), flush=True)
 
 
+def fx_stream_bench(args):
+    """The FX correlator as a real-time pipeline: for each 8192-sample gulp the
+    F-engine channelises the 512 ADC inputs (2398 channels) into the next slot
+    of the X-engine's 4-slot device ring on the ring's ingest stream, and the
+    X-engine integrates it on its compute stream, dumping every 26 gulps; the
+    F-engine of one gulp overlaps the X-engine of the one before. Reports the
+    sustained real-time factor and per-gulp latency percentiles."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1411_3751_amd import FEngine, Stream
+
+    torch.cuda.set_device(0)
+    c = FENGINE_CFG
+    N, M, F, T = c["n_inputs"], c["n_spectra"], c["n_chans"], 8192
+    S = FE_P * (M + FE_TAPS - 1)
+    log("generating %d x %d ADC samples on the device ..." % (N, S))
+    d_adc = synth.adc_device(c["seed"], N, S, "cuda")
+    torch.cuda.synchronize()
+    fe = FEngine(N, c["chan0"], F, c["gain"])
+    sub = dict(n_inputs=N, n_chans=F, n_time=T, in_bits=4)
+    slots, every = 4, args.dump_every
+    gulp_s = T / CHANNEL_HZ
+
+    def feed(st, cnt):
+        for _ in range(cnt):
+            ptr, ist = st.next_slot()
+            for m0 in range(0, T, M):
+                fe.run_ptr(d_adc.data_ptr(), S, M, ptr + m0 * F * N, 0, ist)
+            st.push()
+
+    n = args.steps
+    with Stream(sub, n_slots=slots, dump_every=every) as st:
+        feed(st, slots)
+        st.gulp_times(slots - 1)
+        t0 = time.perf_counter()
+        feed(st, n)
+        st.gulp_times(slots + n - 1)
+        wall = time.perf_counter() - t0
+        lat = [st.gulp_times(g) for g in range(slots, slots + n)]
+    fe.close()
+    rdy = np.array([r for _, r in lat])
+    arr = np.array([a for a, _ in lat])
+    rtf = n * gulp_s / wall
+    res = {"metric": "FX correlator streaming real-time factor at N=512 (F-engine into the X-engine ring)",
+           "value": round(rtf, 2), "unit": "x real time", "n_gpus": 1, "steps": n,
+           "warmup": slots, "ms_per_step": round(1e3 * wall / n, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32+int8", "data": "synthetic",
+           "config": {"workload": "fx_stream_512", "n_inputs": N, "n_chans": F, "n_time": T,
+                      "ring_slots": slots, "dump_every": every, "chan0": c["chan0"],
+                      "fft": FE_P, "taps": FE_TAPS, "gain": c["gain"]},
+           "gulp_ms_p50": round(float(np.percentile(rdy, 50)), 3),
+           "gulp_ms_p99": round(float(np.percentile(rdy, 99)), 3),
+           "arrival_to_done_ms_p50": round(float(np.percentile(arr, 50)), 3),
+           "arrival_to_done_ms_p99": round(float(np.percentile(arr, 99)), 3)}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -554,6 +613,8 @@ def main():
                     help="time the F-engine (PFB + FFT + 4+4-bit requantisation) instead")
     ap.add_argument("--fx", action="store_true",
                     help="time F-engine + X-engine per 8192-sample gulp (512 inputs, 2398 channels)")
+    ap.add_argument("--fx-stream", action="store_true",
+                    help="the same as a pipeline through the X-engine's streaming ring")
     ap.add_argument("--stream-gulps", type=int, default=260)
     ap.add_argument("--stream-h2d-gulps", type=int, default=12,
                     help="stream mode: gulps timed with the input copied from pinned host memory "
@@ -562,6 +623,12 @@ def main():
     ap.add_argument("--pace", type=float, default=4.0,
                     help="latency run: gulps arrive at this multiple of the real-time rate")
     args = ap.parse_args()
+    if args.fx_stream:
+        if args.gpus != 1:
+            print("bench.py measures one GPU (--gpus %d requested)" % args.gpus, file=sys.stderr)
+            sys.exit(2)
+        fx_stream_bench(args)
+        return
     if args.fx:
         if args.gpus != 1:
             print("bench.py measures one GPU (--gpus %d requested)" % args.gpus, file=sys.stderr)

@@ -513,6 +513,15 @@ class FEngine:
             ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(spec.data_ptr() if spec is not None else 0),
             ctypes.c_void_p(_stream_handle(stream))))
 
+    def run_ptr(self, d_adc: int, adc_stride: int, n_spectra: int, d_out: int, d_spec: int = 0,
+                stream=None):
+        """run() on raw device pointers (e.g. a streaming ring slot): int8
+        [n_inputs][adc_stride] in, uint8 [n_spectra][n_chans][n_inputs] out."""
+        _check(self._lib.xeng_fengine_run(self._fe, ctypes.c_void_p(d_adc), int(adc_stride),
+                                          int(n_spectra), ctypes.c_void_p(d_out),
+                                          ctypes.c_void_p(d_spec or 0),
+                                          ctypes.c_void_p(_stream_handle(stream))))
+
     def close(self):
         if getattr(self, "_fe", None) and self._fe.value:
             rc = self._lib.xeng_fengine_destroy(self._fe)

@@ -188,6 +188,38 @@ def test_fengine_feeds_xengine(torch_cuda):
     np.testing.assert_array_equal(got, narrow(correlate(ref_codes, 4)))
 
 
+def test_fengine_into_stream_ring(torch_cuda):
+    """The FX pipeline: the F-engine writes each gulp straight into the X-engine
+    ring slot on the ring's ingest stream (raw-pointer call). The ring's dump
+    must equal the X-engine run on the same F-engine output produced by
+    ordinary calls. The two components are each checked against their
+    references above; this checks their composition through the ring."""
+    torch = torch_cuda
+    from paper_1411_3751_amd import Correlator, FEngine, Stream
+    N, M, chan0, F, G = 16, 64, 1380, 24, 2          # gulp = 64 spectra, dump after 2 gulps
+    S = P * (G * M + TAPS - 1)
+    adc = synth.adc(41, N, S)
+    d_adc = torch.from_numpy(adc).cuda()
+    gain = fe.gain_for_rms(adc, 2.5, 1250, 2398)
+    codes = torch.empty((G * M, F, N), dtype=torch.uint8, device="cuda")
+    hd = [torch.empty((F, N * (N + 1) // 2, 2), dtype=torch.int32, pin_memory=True)]
+    with FEngine(N, chan0, F, gain) as f:
+        f.run(d_adc, G * M, codes)
+        torch.cuda.synchronize()
+        with Stream(dict(n_inputs=N, n_chans=F, n_time=M), n_slots=2, dump_every=G, host_dumps=hd) as st:
+            for g in range(G):
+                ptr, ist = st.next_slot()
+                f.run_ptr(d_adc.data_ptr() + g * M * P, S, M, ptr, 0, ist)
+                st.push()
+            st.dump_wait(0)
+            got = hd[0].numpy().copy()
+    with Correlator([dict(n_inputs=N, n_chans=F, n_time=G * M)]) as xc:
+        xc.correlate([codes])
+        want = xc.dump()[0].cpu().numpy()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(got, want)
+
+
 def test_fengine_errors(torch_cuda):
     torch = torch_cuda
     from paper_1411_3751_amd import FEngine, XengError
