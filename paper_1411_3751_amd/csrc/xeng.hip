@@ -412,6 +412,8 @@ struct SchedChoice {
 std::mutex g_tune_mu;
 std::map<SubKey, SubChoice> g_tune_sub;
 std::map<std::vector<SubKey>, SchedChoice> g_tune_sched;
+// per set of shapes: the choices of a batch tuned as a whole
+std::map<std::vector<SubKey>, std::vector<SubChoice>> g_tune_set;
 
 SubKey key_of(const xeng_subarray &c) { return SubKey{c.n_inputs, c.n_chans, c.n_time, c.in_bits, c.engine}; }
 
@@ -434,13 +436,19 @@ void apply_tuning_cache(xeng_ctx *ctx)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     bool all = true;
-    for (Sub &s : ctx->subs) {
-        auto it = g_tune_sub.find(key_of(s.cfg));
-        if (it == g_tune_sub.end()) {
-            all = false;
-            continue;
+    auto set_it = g_tune_set.find(keys_of(ctx));
+    if (set_it != g_tune_set.end()) {
+        for (size_t k = 0; k < ctx->subs.size(); ++k)
+            set_choice(ctx->subs[k], set_it->second[k].wave, set_it->second[k].wt);
+    } else {
+        for (Sub &s : ctx->subs) {
+            auto it = g_tune_sub.find(key_of(s.cfg));
+            if (it == g_tune_sub.end()) {
+                all = false;
+                continue;
+            }
+            set_choice(s, it->second.wave, it->second.wt);
         }
-        set_choice(s, it->second.wave, it->second.wt);
     }
     auto it = g_tune_sched.find(keys_of(ctx));
     if (it != g_tune_sched.end()) {

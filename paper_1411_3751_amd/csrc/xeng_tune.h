@@ -6,8 +6,11 @@
 // and the register-staging kernel with 32, 64 or 128-input tiles), keeps the
 // fastest per subarray, then times the schedule options of the batched
 // persistent launch (workgroups per CU, tile order) with all subarrays
-// together. Choices go to a process-wide cache keyed by the subarray shapes,
-// which xeng_create consults.
+// together, and finally whole steps with every subarray the persistent kernel
+// can run moved into that one launch (then handed back one at a time while
+// that helps). Choices go to a process-wide cache
+// keyed by the subarray shapes (per shape for a subarray alone, per set of
+// shapes for a batch), which xeng_create consults.
 #pragma once
 
 namespace {
@@ -129,29 +132,83 @@ int xeng_autotune(xeng_ctx *ctx, const void *const *d_samples, int reps)
         }
         set_choice(s, pick.wave, pick.wt);
     }
-    // (2) schedule of the batched persistent launch, all subarrays together
-    const int opts[4][2] = {{2, 0}, {2, 1}, {1, 0}, {1, 1}};
+    // the picks of each subarray timed alone (kept for contexts of that shape)
+    std::vector<SubChoice> alone;
+    for (const Sub &s : ctx->subs) alone.push_back(SubChoice{s.wave, s.wt});
+    // (2) schedule of the batched persistent launch, all subarrays together:
+    // whole steps under each schedule option
+    auto tune_schedule = [&](float &best, int &bw, int &bo) -> int {
+        const int opts[4][2] = {{2, 0}, {2, 1}, {1, 0}, {1, 1}};
+        bool any_wave = false;
+        for (const Sub &s : ctx->subs) any_wave |= s.wave;
+        for (int q = 0; q < (any_wave ? 4 : 1); ++q) {
+            ctx->wg_per_cu = opts[q][0];
+            ctx->order = opts[q][1];
+            int rc = replan(ctx);
+            if (rc) return rc;
+            float ms = 0.f;
+            rc = time_runs(ctx, reps, [&]() { return launch_all(ctx, d_samples); }, ms);
+            if (rc) return rc;
+            if (q == 0 || ms < best) {
+                best = ms;
+                bw = opts[q][0];
+                bo = opts[q][1];
+            }
+        }
+        return XENG_OK;
+    };
     float best = 0.f;
     int bw = 2, bo = 0;
-    bool any_wave = false;
-    for (const Sub &s : ctx->subs) any_wave |= s.wave;
-    for (int q = 0; q < (any_wave ? 4 : 1); ++q) {
-        ctx->wg_per_cu = opts[q][0];
-        ctx->order = opts[q][1];
-        int rc = replan(ctx);
+    int rc = tune_schedule(best, bw, bo);
+    if (rc) return rc;
+    // (3) the batch as a whole. Step (1) times each subarray alone, but one
+    // persistent launch over several subarrays balances its workgroups far
+    // better than any of them alone (more tiles per workgroup), so also time
+    // whole steps with every subarray the persistent kernel can take on it,
+    // and keep whichever assignment is faster.
+    bool can_move = false;
+    for (const Sub &s : ctx->subs) can_move |= wave_path(s.cfg) && !s.wave;
+    if (ctx->subs.size() > 1 && can_move) {
+        for (Sub &s : ctx->subs)
+            if (wave_path(s.cfg)) set_choice(s, true, s.wt);
+        float best_all = 0.f;
+        int bw_all = 2, bo_all = 0;
+        rc = tune_schedule(best_all, bw_all, bo_all);
         if (rc) return rc;
-        float ms = 0.f;
-        rc = time_runs(ctx, reps, [&]() { return launch_all(ctx, d_samples); }, ms);
-        if (rc) return rc;
-        if (q == 0 || ms < best) {
-            best = ms;
-            bw = opts[q][0];
-            bo = opts[q][1];
+        if (best_all < best) {
+            best = best_all;
+            bw = bw_all;
+            bo = bo_all;
+            // then hand back, smallest N first, each subarray whose own pick
+            // was the register kernel, while whole steps get faster
+            std::vector<size_t> order_n(ctx->subs.size());
+            std::iota(order_n.begin(), order_n.end(), (size_t)0);
+            std::stable_sort(order_n.begin(), order_n.end(), [&](size_t a, size_t b) {
+                return ctx->subs[a].cfg.n_inputs < ctx->subs[b].cfg.n_inputs;
+            });
+            ctx->wg_per_cu = bw;
+            ctx->order = bo;
+            for (size_t k : order_n) {
+                Sub &s = ctx->subs[k];
+                if (alone[k].wave || !s.wave || s.cfg.engine == XENG_ENGINE_FP8) continue;
+                const int wt_now = s.wt;
+                set_choice(s, false, alone[k].wt);
+                rc = replan(ctx);
+                if (rc) return rc;
+                float ms = 0.f;
+                rc = time_runs(ctx, reps, [&]() { return launch_all(ctx, d_samples); }, ms);
+                if (rc) return rc;
+                if (ms < best) best = ms;
+                else set_choice(s, true, wt_now);
+            }
+        } else {
+            for (size_t k = 0; k < ctx->subs.size(); ++k)
+                set_choice(ctx->subs[k], alone[k].wave, alone[k].wt);
         }
     }
     ctx->wg_per_cu = bw;
     ctx->order = bo;
-    int rc = replan(ctx);
+    rc = replan(ctx);
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     for (Sub &s : ctx->subs) {
@@ -160,7 +217,10 @@ int xeng_autotune(xeng_ctx *ctx, const void *const *d_samples, int reps)
     }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        for (const Sub &s : ctx->subs) g_tune_sub[key_of(s.cfg)] = SubChoice{s.wave, s.wt};
+        for (size_t k = 0; k < ctx->subs.size(); ++k) g_tune_sub[key_of(ctx->subs[k].cfg)] = alone[k];
+        std::vector<SubChoice> chosen;
+        for (const Sub &s : ctx->subs) chosen.push_back(SubChoice{s.wave, s.wt});
+        g_tune_set[keys_of(ctx)] = chosen;
         g_tune_sched[keys_of(ctx)] = SchedChoice{bw, bo};
     }
     ctx->tuned = true;
