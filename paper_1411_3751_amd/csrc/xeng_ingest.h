@@ -9,7 +9,7 @@
 //                         the packet's block in the bitmap (a vector atomic
 //                         OR from one lane), copy the payload rows to
 //                         [time][chan][input] in 16-, 4- or 1-byte units
-//   ingest_fill_kernel    one wave per expected block: zero-fill the
+//   ingest_fill_kernel    one wave per 64 expected blocks: zero-fill the
 //                         blocks whose bit is clear and count them
 #pragma once
 
@@ -26,13 +26,26 @@ struct IngestGeom {
 
 enum { CNT_RECEIVED = 0, CNT_MISSING = 1, CNT_DUPLICATE = 2, CNT_REJECTED = 3 };
 
+// The counters are spread over CNT_SLOTS copies, one 128-byte line each, and
+// summed on the host: one packet per wave adds to them, and a single address
+// would serialise every one of those atomics in one L2 channel.
+constexpr int CNT_SLOTS = 64;
+constexpr int CNT_STRIDE = 16; // counters per slot line (4 used)
+
+__device__ __forceinline__ unsigned long long *cnt_slot(unsigned long long *counts, int64_t wave)
+{
+    return counts + (size_t)(wave & (CNT_SLOTS - 1)) * CNT_STRIDE;
+}
+
 __global__ void ingest_clear_kernel(uint32_t *bitmap, int64_t n_words,
                                     unsigned long long *counts)
 {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_words;
          k += (int64_t)gridDim.x * blockDim.x)
         bitmap[k] = 0u;
-    if (blockIdx.x == 0 && threadIdx.x < 4) counts[threadIdx.x] = 0ull;
+    if (blockIdx.x == 0)
+        for (int k = threadIdx.x; k < CNT_SLOTS * 4; k += blockDim.x)
+            counts[(size_t)(k >> 2) * CNT_STRIDE + (k & 3)] = 0ull;
 }
 
 template <int UNIT>
@@ -88,7 +101,8 @@ __global__ __launch_bounds__(256) void ingest_scatter_kernel(const uint8_t *__re
             claim = (old >> (b & 31)) & 1u ? 2 : 1;
         }
         if (lane == 0)
-            atomicAdd(&counts[claim == 1 ? CNT_RECEIVED : claim == 2 ? CNT_DUPLICATE : CNT_REJECTED],
+            atomicAdd(&cnt_slot(counts, p)[claim == 1 ? CNT_RECEIVED : claim == 2 ? CNT_DUPLICATE
+                                                                               : CNT_REJECTED],
                       1ull);
         if (claim != 1) continue;
         const uint8_t *src = pk + 16;
@@ -98,7 +112,9 @@ __global__ __launch_bounds__(256) void ingest_scatter_kernel(const uint8_t *__re
     }
 }
 
-// one wave per expected block: zero-fill the blocks whose bit is clear
+// one wave per 64 consecutive expected blocks: a ballot over their bitmap
+// bits finds the missing ones (most are present), which the wave then
+// zero-fills one after the other; one count per wave
 template <int UNIT>
 __global__ __launch_bounds__(256) void ingest_fill_kernel(IngestGeom g, uint8_t *__restrict__ gulp,
                                                           const uint32_t *bitmap,
@@ -109,16 +125,22 @@ __global__ __launch_bounds__(256) void ingest_fill_kernel(IngestGeom g, uint8_t 
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int32_t units_row = g.pi * g.bps / UNIT;
     const int32_t units = units_row * g.pt * g.pc;
-    for (int64_t b = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); b < n_blocks;
-         b += waves) {
-        if ((bitmap[b >> 5] >> (b & 31)) & 1u) continue;
-        if (lane == 0) atomicAdd(&counts[CNT_MISSING], 1ull);
-        const int64_t ib = b % g.nb_i, fb = (b / g.nb_i) % g.nb_f, tb = b / ((int64_t)g.nb_i * g.nb_f);
-        for (int32_t u = lane; u < units; u += 64) {
-            uint8_t *dst = block_unit(gulp, g, tb * g.pt, fb * g.pc, ib * g.pi, u, units_row, UNIT);
-            if constexpr (UNIT == 16) *(uint4 *)dst = make_uint4(0u, 0u, 0u, 0u);
-            else if constexpr (UNIT == 4) *(uint32_t *)dst = 0u;
-            else *dst = 0;
+    for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w * 64 < n_blocks;
+         w += waves) {
+        const int64_t b = w * 64 + lane;
+        const bool missing = b < n_blocks && !((bitmap[b >> 5] >> (b & 31)) & 1u);
+        uint64_t todo = __ballot(missing);
+        if (lane == 0 && todo) atomicAdd(&cnt_slot(counts, w)[CNT_MISSING], (unsigned long long)__popcll(todo));
+        while (todo) {
+            const int64_t bm = w * 64 + __ffsll((long long)todo) - 1;
+            todo &= todo - 1;
+            const int64_t ib = bm % g.nb_i, fb = (bm / g.nb_i) % g.nb_f, tb = bm / ((int64_t)g.nb_i * g.nb_f);
+            for (int32_t u = lane; u < units; u += 64) {
+                uint8_t *dst = block_unit(gulp, g, tb * g.pt, fb * g.pc, ib * g.pi, u, units_row, UNIT);
+                if constexpr (UNIT == 16) *(uint4 *)dst = make_uint4(0u, 0u, 0u, 0u);
+                else if constexpr (UNIT == 4) *(uint32_t *)dst = 0u;
+                else *dst = 0;
+            }
         }
     }
 }
@@ -172,7 +194,9 @@ int xeng_ingest_create(const xeng_subarray *sub, const xeng_packet_format *fmt, 
     ig->n_blocks = (int64_t)g.nb_t * g.nb_f * g.nb_i;
     ig->n_words = (ig->n_blocks + 31) / 32;
     hipError_t e = hipMalloc((void **)&ig->d_bitmap, sizeof(uint32_t) * (size_t)ig->n_words);
-    if (e == hipSuccess) e = hipMalloc((void **)&ig->d_counts, 4 * sizeof(unsigned long long));
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&ig->d_counts,
+                      (size_t)xeng::CNT_SLOTS * xeng::CNT_STRIDE * sizeof(unsigned long long));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         if (ig->d_bitmap) (void)hipFree(ig->d_bitmap);
@@ -219,7 +243,7 @@ int xeng_ingest_gulp(xeng_ingest *ig, const void *d_packets, int64_t n_packets, 
                                n_packets, g, gp, ig->d_bitmap, ig->d_counts);
         HIP_TRY(hipGetLastError());
     }
-    const unsigned fb = (unsigned)std::min<int64_t>((ig->n_blocks + 3) / 4, 65536);
+    const unsigned fb = (unsigned)std::min<int64_t>((ig->n_blocks + 255) / 256, 65536);
     if (g.unit == 16)
         hipLaunchKernelGGL(xeng::ingest_fill_kernel<16>, dim3(fb < 1 ? 1 : fb), dim3(256), 0, st, g,
                            (uint8_t *)d_gulp, ig->d_bitmap, ig->d_counts);
@@ -238,8 +262,11 @@ int xeng_ingest_stats_get(xeng_ingest *ig, xeng_ingest_stats *out)
 {
     if (!ig || !out) return fail(XENG_EINVAL, "NULL argument");
     HIP_TRY(hipStreamSynchronize(ig->last));
-    unsigned long long c[4];
-    HIP_TRY(hipMemcpy(c, ig->d_counts, sizeof c, hipMemcpyDeviceToHost));
+    unsigned long long slots[xeng::CNT_SLOTS * xeng::CNT_STRIDE];
+    HIP_TRY(hipMemcpy(slots, ig->d_counts, sizeof slots, hipMemcpyDeviceToHost));
+    unsigned long long c[4] = {0ull, 0ull, 0ull, 0ull};
+    for (int k = 0; k < xeng::CNT_SLOTS; ++k)
+        for (int j = 0; j < 4; ++j) c[j] += slots[k * xeng::CNT_STRIDE + j];
     out->received = (int64_t)c[xeng::CNT_RECEIVED];
     out->missing = (int64_t)c[xeng::CNT_MISSING];
     out->duplicate = (int64_t)c[xeng::CNT_DUPLICATE];
