@@ -309,7 +309,7 @@ def batch_bench(args):
     stream = torch.cuda.current_stream()
     with Correlator(subs, stream=stream) as c:
         t0 = time.perf_counter()
-        c.autotune(dev, reps=3)
+        c.autotune(dev, reps=5)
         tune_s = time.perf_counter() - t0
         plan = c.plan()
         log("plan:", json.dumps(plan))
