@@ -342,6 +342,56 @@ def batch_bench(args):
     print(json.dumps(res), flush=True)
 
 
+def sweep_bench(args):
+    """The X-engine across N at T = 8192 (4-bit, int8 engine, correlate
+    alone, default plan), F chosen so each shape does comparable work; one
+    JSON line whose value is the N = 512 shape."""
+    import torch
+
+    from paper_1411_3751_amd import Correlator
+
+    torch.cuda.set_device(0)
+    T = 8192
+    shapes = [(128, 1024), (256, 512), (512, 128), (768, 96), (1024, 64), (2048, 16), (4096, 4)]
+    rows = []
+    g = torch.Generator(device="cuda").manual_seed(11)
+    for N, F in shapes:
+        x = torch.randint(0, 256, (T, F, N), dtype=torch.int32, device="cuda", generator=g).to(torch.uint8)
+        with Correlator([dict(n_inputs=N, n_chans=F, n_time=T)]) as c:
+            kern = c.plan()["subarrays"][0]["kernel"]
+            for _ in range(args.warmup):
+                c.correlate([x])
+                c.reset()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                c.correlate([x])
+                c.reset()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+        del x
+        ops = F * N * (N + 1) // 2 * T * OPS_PER_CMAC
+        nb = (N + 127) // 128
+        computed = (nb * (nb + 1) // 2 - nb) * 16384 + nb * 12288  # cells per channel
+        rows.append({"n_inputs": N, "n_chans": F, "kernel": kern, "ms": round(ms, 4),
+                     "tops": round(ops / (ms * 1e-3) / 1e12, 1),
+                     "pct_int8_peak": round(100.0 * ops / (ms * 1e-3) / PEAK_INT8_OPS, 2),
+                     "useful_fraction": round(N * (N + 1) / 2 / computed, 3)})
+        log("N=%d F=%d %s %.4f ms" % (N, F, kern, ms))
+    main_row = [r for r in rows if r["n_inputs"] == 512][0]
+    res = {"metric": METRIC, "value": main_row["tops"], "unit": "Tops/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_row["ms"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int8",
+           "data": "synthetic",
+           "config": {"workload": "sweep_n", "n_time": T, "in_bits": 4, "engine": "i8",
+                      "step": "correlate alone", "value_of": "N=512, F=128"},
+           "sweep": rows}
+    print(json.dumps(res), flush=True)
+
+
 def ingest_bench(args):
     """Packet ingest: the LEDA gulp (N=512, 128 channels, 8192 samples) cut
     into F-engine packets of 4 times x 16 channels x 64 inputs (4 KB payload),
@@ -626,6 +676,8 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="run the batched uneven-subarray configuration instead (autotuned, "
                          "graph-captured)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="time the X-engine alone across N = 128 ... 4096 at T = 8192")
     ap.add_argument("--ingest", action="store_true",
                     help="time the packet ingest (corner turn of F-engine packets) instead")
     ap.add_argument("--fengine", action="store_true",
@@ -659,6 +711,12 @@ def main():
             print("bench.py measures one GPU (--gpus %d requested)" % args.gpus, file=sys.stderr)
             sys.exit(2)
         fengine_bench(args)
+        return
+    if args.sweep:
+        if args.gpus != 1:
+            print("bench.py measures one GPU (--gpus %d requested)" % args.gpus, file=sys.stderr)
+            sys.exit(2)
+        sweep_bench(args)
         return
     if args.ingest:
         if args.gpus != 1:
