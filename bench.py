@@ -23,7 +23,8 @@ sys.path.insert(0, ROOT)
 METRIC = ("complex MACs/s (Tops/s) at N=512, % int8 MFMA peak; real-time factor; "
           "p99 gulp ms")
 OPS_PER_CMAC = 8                 # 4 real multiply-adds = 8 int8 ops
-PEAK_INT8_OPS = 5.0e15           # MI355X dense int8 MFMA, ops/s
+PEAK_INT8_OPS = 5.0e15           # MI355X dense int8 MFMA, ops/s (2.4 GHz)
+PEAK_HBM_GBS = 8000.0            # MI355X HBM3E, GB/s
 CHANNEL_HZ = 24.0e3              # channel width of the paper's F-engine (Section 2)
 
 
@@ -691,8 +692,12 @@ def main():
                     help="stream mode: gulps timed with the input copied from pinned host memory "
                          "(0 skips that phase)")
     ap.add_argument("--dump-every", type=int, default=26)
-    ap.add_argument("--pace", type=float, default=4.0,
+    ap.add_argument("--pace", type=float, default=10.0,
                     help="latency run: gulps arrive at this multiple of the real-time rate")
+    ap.add_argument("--settle-s", type=float, default=1.0,
+                    help="seconds of untimed back-to-back steps before the warm-up steps")
+    ap.add_argument("--no-stream", action="store_true",
+                    help="skip the streaming figures of the default line")
     args = ap.parse_args()
     if args.fx_stream:
         if args.gpus != 1:
@@ -751,6 +756,12 @@ def main():
               "requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    xengine_bench(args)
+
+
+def xengine_bench(args):
+    """The headline step on one workload: xeng_correlate + xeng_dump(device,
+    reset) with the samples resident in HBM."""
     import torch
 
     import synth
@@ -773,42 +784,58 @@ def main():
                             engine=1 if engine == "fp8" else 0)], stream=stream)
     if args.autotune:
         corr.autotune([d_samples])
-    log("plan:", json.dumps(corr.plan()))
+    plan = corr.plan()
+    log("plan:", json.dumps(plan))
 
     def step():
         corr.correlate([d_samples])
         corr.dump([out], reset=True)
 
+    # settle: under sustained MFMA load the clock first overshoots downwards
+    # and recovers over the next tens of milliseconds; a fixed stretch of
+    # untimed steps puts the warm-up and the timed steps in the settled state
+    settle_steps = settle(step, args.settle_s)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
 
-    # whole steps; each correlate call is one launch of the tile kernel, and
-    # an event pair around it on the same stream times that launch
+    # timed region: K whole steps between two events, nothing else enqueued
+    clock = ClockSampler()
     n = args.steps
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    clock.start()
+    t_start.record(stream)
+    for _ in range(n):
+        step()
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    clock.stop()
+    ms_step = t_start.elapsed_time(t_end) / n
+
+    # kernel pass (after the timed region): an event pair on the stream
+    # around each correlate call times that launch of the tile kernel
     k_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
             for _ in range(n)]
-    torch.cuda.synchronize()
-    t_start.record(stream)
     for k in range(n):
         k_ev[k][0].record(stream)
         corr.correlate([d_samples])
         k_ev[k][1].record(stream)
         corr.dump([out], reset=True)
-    t_end.record(stream)
     torch.cuda.synchronize()
-    ms_step = t_start.elapsed_time(t_end) / n
-    k_ms = sorted(a.elapsed_time(b) for a, b in k_ev)
+    k_ms = [a.elapsed_time(b) for a, b in k_ev]
     ms_kernel = sum(k_ms) / n
     corr.close()
+    del d_samples, out
+    torch.cuda.empty_cache()
 
     ops_step = cmac_per_step * OPS_PER_CMAC
     value = ops_step / (ms_step * 1e-3) / 1e12
     achieved = ops_step / (ms_kernel * 1e-3) / 1e12
     peak = PEAK_INT8_OPS / 1e12
-    stream_s = T / CHANNEL_HZ
+    small = N < 256  # tiny and n64: the samples and the output, not the MFMAs, bound the step
+    hbm_bytes = N * F * T * (in_bits // 4) + F * tri * 8
     res = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -823,22 +850,195 @@ def main():
         "dtype": "fp8_e4m3" if engine == "fp8" else "int8",
         "data": "synthetic",
         "config": {"workload": name, "n_inputs": N, "n_chans": F, "n_time": T,
-                   "in_bits": in_bits, "engine": engine, "autotuned": bool(args.autotune)},
+                   "in_bits": in_bits, "engine": engine, "autotuned": bool(args.autotune),
+                   "step": "correlate + dump (device, reset)",
+                   "kernel": plan["subarrays"][0]["kernel"]},
+        "settle_steps": settle_steps,
+        "settle_s": args.settle_s,
         "cmac_per_s": cmac_per_step / (ms_step * 1e-3),
         "pct_int8_peak": round(100.0 * value / peak, 2),
-        "rtf_gulp": round(stream_s / (ms_step * 1e-3), 1),
+        # one gulp of this workload (T samples at 24 kHz per channel) against its step time
+        "rtf_this_gulp": round(T / CHANNEL_HZ / (ms_step * 1e-3), 1),
+        "rtf_this_gulp_def": "%d-sample gulp of %d channels (%.3f s of stream) / step time" % (
+            T, F, T / CHANNEL_HZ),
         # minimum HBM bytes of a step: the samples once plus the visibilities once
-        "hbm_gbs_algorithmic": round((N * F * T * (in_bits // 4) + F * tri * 8) / (ms_step * 1e-3) / 1e9, 1),
+        "hbm_gbs_algorithmic": round(hbm_bytes / (ms_step * 1e-3) / 1e9, 1),
         "ms_kernel": round(ms_kernel, 4),
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "traffic": hbm_traffic(KERNEL, name) if engine == "i8" and in_bits == 4
-                     else None},
+        "ms_kernel_p50": round(sorted(k_ms)[n // 2], 4),
     }
+    mhz = clock.mhz()
+    if mhz:
+        res["gfxclk_mhz_timed"] = round(mhz, 0)
+        res["pct_int8_peak_at_measured_clock"] = round(
+            100.0 * value / (PEAK_INT8_OPS * mhz / 2400.0 / 1e12), 2)
+        res["clock_source"] = clock.source
+    if small:
+        res["roofline"] = {"bound": "hbm", "achieved": round(hbm_bytes / (ms_kernel * 1e-3) / 1e9, 1),
+                           "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                           "frac": round(hbm_bytes / (ms_kernel * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                           "traffic": None}
+    else:
+        res["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
+                           "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                           "traffic": hbm_traffic(KERNEL, name) if engine == "i8" and in_bits == 4
+                           else None}
+    if name == "leda_gulp" and not args.no_stream:
+        res.update(stream_figures(args))
     if not args.no_cpu:
         log("timing the CPU oracle on a sample ...")
         res["cpu_baseline"] = cpu_baseline(samples, N, F, T, in_bits)
     print(json.dumps(res), flush=True)
+
+
+def settle(step, seconds):
+    """Run back-to-back untimed steps for about `seconds`; returns the count."""
+    import torch
+    if seconds <= 0:
+        return 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(10):
+            step()
+        n += 10
+        torch.cuda.synchronize()
+    return n
+
+
+class ClockSampler:
+    """Samples the GPU's graphics clock (amdsmi GPU metrics) in a background
+    thread while a region runs; mhz() is the mean of the samples, or None
+    where the metrics are not readable."""
+
+    def __init__(self, period_s=0.002):
+        self.period = period_s
+        self.samples = []
+        self.source = None
+        self._h = None
+        self._stop = False
+        self._t = None
+        try:
+            import amdsmi
+            amdsmi.amdsmi_init()
+            self._smi = amdsmi
+            self._h = amdsmi.amdsmi_get_processor_handles()[0]
+        except Exception as e:  # no amdsmi, no device, no permission
+            log("clock sampling unavailable: %s" % e)
+            self._h = None
+
+    def _read(self):
+        m = self._smi.amdsmi_get_gpu_metrics_info(self._h)
+        for key in ("current_gfxclk", "average_gfxclk_frequency"):
+            v = m.get(key)
+            if isinstance(v, (int, float)) and 0 < v < 10000:
+                self.source = "amdsmi gpu_metrics " + key
+                return float(v)
+        v = m.get("current_gfxclks")
+        if isinstance(v, (list, tuple)):
+            vals = [float(x) for x in v if isinstance(x, (int, float)) and 0 < x < 10000]
+            if vals:
+                self.source = "amdsmi gpu_metrics current_gfxclks (mean over XCDs)"
+                return sum(vals) / len(vals)
+        return None
+
+    def _run(self):
+        while not self._stop:
+            try:
+                v = self._read()
+            except Exception:
+                v = None
+            if v:
+                self.samples.append(v)
+            time.sleep(self.period)
+
+    def start(self):
+        if self._h is None:
+            return
+        import threading
+        self._stop = False
+        self._t = threading.Thread(target=self._run, daemon=True)
+        self._t.start()
+
+    def stop(self):
+        if self._t is not None:
+            self._stop = True
+            self._t.join()
+            self._t = None
+
+    def mhz(self):
+        return sum(self.samples) / len(self.samples) if self.samples else None
+
+
+def stream_figures(args):
+    """Real-time figures of the streaming configuration (N = 512, 2400
+    channels of 24 kHz, 8192-sample gulps into a 4-slot device ring, dump
+    every 26 gulps copied to pinned host buffers): the sustained rate through
+    the ring with the slots filled once by the device generator (samples
+    resident in HBM, like the step above), and the arrival-to-done latency of
+    gulps fed at a fixed multiple of the real-time rate."""
+    import numpy as np
+    import torch
+
+    import synth
+    import synth.gpu
+    from paper_1411_3751_amd import Stream
+
+    synth.gpu.build()
+    N, F, T = STREAM_CFG["n_inputs"], STREAM_CFG["n_chans"], STREAM_CFG["n_time"]
+    every, slots, n = args.dump_every, 4, args.stream_gulps
+    seed = synth.SEED_BASE + 4
+    tone = (synth.TONE_AMP, lambda t: synth.drift_phase(t, T), synth.tone_channels(F))
+    gen = synth.gpu.DeviceStream(seed, F, N, 4, 2.5, tone=tone, t_total=slots * T)
+    tri = N * (N + 1) // 2
+    cmac_gulp = F * tri * T
+    gulp_s = T / CHANNEL_HZ
+    hd = [torch.empty((F, tri, 2), dtype=torch.int32, pin_memory=True) for _ in range(2)]
+    sub = dict(STREAM_CFG)
+    log("stream figures: N=%d F=%d T=%d, %d gulps ..." % (N, F, T, n))
+    res = {}
+    with Stream(sub, n_slots=slots, dump_every=every, host_dumps=hd) as st:
+        for g in range(slots):
+            ptr, ist = st.next_slot()
+            gen.fill(ptr, g * T, T, ist)
+            st.push()
+        st.gulp_times(slots - 1)
+        # sustained: every gulp reuses its slot's contents, as fast as it goes
+        t0 = time.perf_counter()
+        for _ in range(n):
+            st.next_slot()
+            st.push()
+        st.gulp_times(slots + n - 1)
+        wall = time.perf_counter() - t0
+        res["stream_rtf"] = round(n * gulp_s / wall, 2)
+        res["stream_tops"] = round(cmac_gulp * n * OPS_PER_CMAC / wall / 1e12, 1)
+        res["stream_pct_int8_peak"] = round(100.0 * cmac_gulp * n * OPS_PER_CMAC / wall / PEAK_INT8_OPS, 2)
+        # paced: a gulp arrives every gulp_s / pace seconds (host clock);
+        # latency = arrival (next_slot) to the end of its correlation (and of
+        # its dump when it completes one)
+        g0 = slots + n
+        pace = args.pace
+        t_next = time.perf_counter()
+        for _ in range(n):
+            while time.perf_counter() < t_next:
+                time.sleep(0.0002)
+            t_next += gulp_s / pace
+            st.next_slot()
+            st.push()
+        lat = np.array([st.gulp_times(g)[0] for g in range(g0, g0 + n)])
+    res["stream_gulp_ms_p50"] = round(float(np.percentile(lat, 50)), 3)
+    res["stream_gulp_ms_p99"] = round(float(np.percentile(lat, 99)), 3)
+    res["stream_gulp_ms_max"] = round(float(lat.max()), 3)
+    res["stream_config"] = {"workload": "stream_2400ch", "n_inputs": N, "n_chans": F, "n_time": T,
+                            "ring_slots": slots, "dump_every": every, "gulps": n,
+                            "pace_x_realtime": pace,
+                            "rtf_def": "%d gulps x %.3f s of stream / wall time, slots filled "
+                                       "once (samples resident in HBM), dumps copied to pinned "
+                                       "host memory" % (n, gulp_s)}
+    log("stream figures: RTF %.1f, %.1f Tops/s, latency p50 %.2f ms p99 %.2f ms" % (
+        res["stream_rtf"], res["stream_tops"], res["stream_gulp_ms_p50"], res["stream_gulp_ms_p99"]))
+    del hd
+    return res
 
 
 if __name__ == "__main__":

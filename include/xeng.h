@@ -177,8 +177,11 @@ typedef struct xeng_graph xeng_graph; /* opaque, library-owned */
  * left so. Each xeng_graph_launch re-runs the step on the same buffers: the
  * caller refills d_samples[s] and reads out[s] (device pointers) around the
  * launches. The graph holds no memset nodes (buffers are cleared by
- * kernels). The graph stays valid while ctx lives; do not interleave its
- * launches with eager calls on ctx without ordering them on one stream.
+ * kernels). The graph keeps its own reference to the tile schedule it was
+ * captured with, so a later xeng_autotune (which replans ctx) does not
+ * invalidate it; it reads and writes ctx's accumulators and so stays valid
+ * while ctx lives. Do not interleave its launches with eager calls on ctx
+ * without ordering them on one stream.
  */
 int xeng_graph_create(xeng_ctx *ctx, const void *const *d_samples, void *const *out,
                       xeng_graph **out_graph);
@@ -243,14 +246,21 @@ int xeng_stream_push(xeng_stream *s, int64_t *gulp);
 int xeng_stream_dump_wait(xeng_stream *s, int64_t d, void **d_dump);
 
 /*
- * Wait for gulp g (one of the last 4096 pushed) and report, in milliseconds,
- * the time from its arrival (next_slot) and from its slot being filled to
- * the end of its correlation (and of its dump, when it completes one).
+ * Wait for gulp g (one of the last 1024 pushed) and report, in milliseconds,
+ * the time from its arrival (the next_slot call that asked for its slot,
+ * including any wait for that slot to come free) and from its slot being
+ * filled to the end of its correlation (and of its dump, when it completes
+ * one).
  */
 int xeng_stream_gulp_times(xeng_stream *s, int64_t g, float *arrive_ms, float *ready_ms);
 
 /* Number of gulps pushed so far. */
 int xeng_stream_gulps(const xeng_stream *s, int64_t *out);
+
+/* Gulps pushed whose correlation (and dump, if they complete one) has not yet
+ * finished on the device: 0 while the engine keeps up; a count that grows
+ * from push to push means gulps arrive faster than they are integrated. */
+int xeng_stream_backlog(xeng_stream *s, int64_t *out);
 
 /* Wait for all work of the stream and release it. NULL is a no-op. */
 int xeng_stream_destroy(xeng_stream *s);

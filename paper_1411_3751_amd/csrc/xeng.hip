@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <numeric>
@@ -73,6 +74,17 @@ struct Sub {
     int n_fast = 0;
 };
 
+// Device memory released by hipFree when its last owner lets go: a plan's
+// tile list is owned by its context and by every graph captured with it, so
+// replanning (autotuning) never frees memory a graph still launches with.
+struct DevFree {
+    void operator()(void *p) const
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+using DevBuf = std::shared_ptr<void>;
+
 // One persistent-kernel launch group: the subarrays it covers and its schedule.
 struct WavePlan {
     int engine = XENG_ENGINE_I8;     // every subarray of a plan uses this engine
@@ -81,6 +93,7 @@ struct WavePlan {
     std::vector<xeng::WgItem> items; // flat, grouped per workgroup
     std::vector<int32_t> wg_begin;   // [n_wg + 1]
     int n_wg = 0;
+    DevBuf d_mem;                    // one allocation: items, then wg_begin
     xeng::WgItem *d_items = nullptr;
     int32_t *d_wg_begin = nullptr;
     double max_wg_cost = 0, mean_wg_cost = 0;
@@ -250,9 +263,17 @@ void build_schedule(WavePlan &p, const std::vector<Sub> &subs, int n_cu, int wg_
 
 int upload_plan(WavePlan &p)
 {
-    HIP_TRY(hipMalloc((void **)&p.d_items,
-                      sizeof(xeng::WgItem) * std::max<size_t>(1, p.items.size())));
-    HIP_TRY(hipMalloc((void **)&p.d_wg_begin, sizeof(int32_t) * p.wg_begin.size()));
+    const size_t item_bytes = (sizeof(xeng::WgItem) * std::max<size_t>(1, p.items.size()) + 255) & ~(size_t)255;
+    const size_t total = item_bytes + sizeof(int32_t) * p.wg_begin.size();
+    void *mem = nullptr;
+    hipError_t e = hipMalloc(&mem, total);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(XENG_ENOMEM, "hipMalloc(%zu) for a tile list: %s", total, hipGetErrorString(e));
+    }
+    p.d_mem = DevBuf(mem, DevFree());
+    p.d_items = (xeng::WgItem *)mem;
+    p.d_wg_begin = (int32_t *)((char *)mem + item_bytes);
     HIP_TRY(hipMemcpy(p.d_items, p.items.data(), sizeof(xeng::WgItem) * p.items.size(),
                       hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(p.d_wg_begin, p.wg_begin.data(), sizeof(int32_t) * p.wg_begin.size(),
@@ -343,14 +364,8 @@ int dump_device(const Sub &s, uint32_t *out, hipStream_t st)
     return XENG_OK;
 }
 
-void free_plans(xeng_ctx *ctx)
-{
-    for (WavePlan &p : ctx->plans) {
-        if (p.d_items) (void)hipFree(p.d_items);
-        if (p.d_wg_begin) (void)hipFree(p.d_wg_begin);
-    }
-    ctx->plans.clear();
-}
+// Drops the context's hold on its tile lists (a graph may still hold them).
+void free_plans(xeng_ctx *ctx) { ctx->plans.clear(); }
 
 // Launch groups of the persistent kernel from the subarrays' kernel choices:
 // per (engine, input width), one group for all its subarrays when each fits

@@ -3,8 +3,10 @@
 // context API); uses only that API and the HIP runtime.
 //
 // Per gulp g (slot g % n_slots):
+//   clock stream  : record arrive[g] when the caller asks for the slot (this
+//                   stream never waits, so the event marks the host's request)
 //   ingest stream : wait slot_free[slot] (gulp g - n_slots correlated),
-//                   record arrive[g], caller's fill work, record ready[g]
+//                   caller's fill work, record ready[g]
 //   compute stream: wait ready[g], xeng_correlate, record slot_free[slot];
 //                   if g completes dump d: wait out_done[d % 2] (dump d - 2
 //                   copied out), xeng_dump into dump buffer d % 2 + reset,
@@ -15,7 +17,7 @@
 
 namespace {
 
-constexpr int STREAM_HIST = 4096; // gulps whose events are kept
+constexpr int STREAM_HIST = 1024; // gulps whose events are kept
 
 struct GulpEv {
     hipEvent_t arrive = nullptr, ready = nullptr, done = nullptr;
@@ -27,6 +29,7 @@ struct xeng_stream {
     xeng_subarray cfg{};
     xeng_ctx *ctx = nullptr;
     hipStream_t s_in = nullptr, s_comp = nullptr, s_out = nullptr;
+    hipStream_t s_clk = nullptr;         // arrival stamps only: never waits
     int n_slots = 0, dump_every = 0;
     size_t gulp_bytes = 0, dump_bytes = 0;
     uint8_t *ring = nullptr;
@@ -50,6 +53,7 @@ void stream_free(xeng_stream *s)
     if (s->s_in) (void)hipStreamSynchronize(s->s_in);
     if (s->s_comp) (void)hipStreamSynchronize(s->s_comp);
     if (s->s_out) (void)hipStreamSynchronize(s->s_out);
+    if (s->s_clk) (void)hipStreamSynchronize(s->s_clk);
     if (s->ctx) xeng_destroy(s->ctx);
     for (hipEvent_t e : s->slot_free)
         if (e) (void)hipEventDestroy(e);
@@ -67,6 +71,7 @@ void stream_free(xeng_stream *s)
     if (s->s_in) (void)hipStreamDestroy(s->s_in);
     if (s->s_comp) (void)hipStreamDestroy(s->s_comp);
     if (s->s_out) (void)hipStreamDestroy(s->s_out);
+    if (s->s_clk) (void)hipStreamDestroy(s->s_clk);
     delete s;
 }
 
@@ -75,6 +80,7 @@ int stream_init(xeng_stream *s)
     HIP_TRY(hipStreamCreateWithFlags(&s->s_in, hipStreamNonBlocking));
     HIP_TRY(hipStreamCreateWithFlags(&s->s_comp, hipStreamNonBlocking));
     HIP_TRY(hipStreamCreateWithFlags(&s->s_out, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&s->s_clk, hipStreamNonBlocking));
     int rc = xeng_create(&s->cfg, 1, s->s_comp, &s->ctx);
     if (rc) return rc;
     hipError_t e = hipMalloc((void **)&s->ring, s->gulp_bytes * (size_t)s->n_slots);
@@ -154,8 +160,10 @@ int xeng_stream_next_slot(xeng_stream *s, void **d_slot, void **ingest_stream)
     const int64_t g = s->n_pushed;
     const int slot = (int)(g % s->n_slots);
     if (!s->have_slot) {
+        // arrival first, on the idle clock stream: the latency then includes
+        // any wait for the slot's previous gulp
+        HIP_TRY(hipEventRecord(s->ev[g % STREAM_HIST].arrive, s->s_clk));
         if (s->slot_used[slot]) HIP_TRY(hipStreamWaitEvent(s->s_in, s->slot_free[slot], 0));
-        HIP_TRY(hipEventRecord(s->ev[g % STREAM_HIST].arrive, s->s_in));
         s->have_slot = true;
     }
     *d_slot = s->ring + (size_t)slot * s->gulp_bytes;
@@ -230,6 +238,24 @@ int xeng_stream_gulps(const xeng_stream *s, int64_t *out)
 {
     if (!s || !out) return fail(XENG_EINVAL, "NULL argument");
     *out = s->n_pushed;
+    return XENG_OK;
+}
+
+int xeng_stream_backlog(xeng_stream *s, int64_t *out)
+{
+    if (!s || !out) return fail(XENG_EINVAL, "NULL argument");
+    // gulps whose correlation (and dump) has not finished: done events
+    // complete in push order on the compute stream, so count back from the
+    // newest until one has completed
+    int64_t n = 0;
+    const int64_t lo = std::max<int64_t>(0, s->n_pushed - STREAM_HIST);
+    for (int64_t g = s->n_pushed - 1; g >= lo; --g) {
+        const hipError_t q = hipEventQuery(s->ev[g % STREAM_HIST].done);
+        if (q == hipSuccess) break;
+        if (q != hipErrorNotReady) return fail(XENG_EHIP, "hipEventQuery: %s", hipGetErrorString(q));
+        ++n;
+    }
+    *out = n;
     return XENG_OK;
 }
 

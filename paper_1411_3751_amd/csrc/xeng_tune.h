@@ -65,8 +65,6 @@ int time_one(xeng_ctx *ctx, int k, const void *const *d_samples, int reps, float
     int rc = upload_plan(p);
     if (!rc) rc = time_runs(ctx, reps, [&]() { return launch_wave(ctx, p, d_samples); }, ms);
     (void)hipStreamSynchronize(ctx->stream);
-    if (p.d_items) (void)hipFree(p.d_items);
-    if (p.d_wg_begin) (void)hipFree(p.d_wg_begin);
     return rc;
 }
 
@@ -89,6 +87,7 @@ int launch_all(xeng_ctx *ctx, const void *const *d_samples)
 struct xeng_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::vector<DevBuf> keep; // tile lists the captured launches read
 };
 
 extern "C" {
@@ -268,6 +267,7 @@ int xeng_graph_create(xeng_ctx *ctx, const void *const *d_samples, void *const *
         return fail(XENG_ENOMEM, "host allocation failed");
     }
     xg->graph = g;
+    for (const WavePlan &p : ctx->plans) xg->keep.push_back(p.d_mem);
     e = hipGraphInstantiate(&xg->exec, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         (void)hipGraphDestroy(g);

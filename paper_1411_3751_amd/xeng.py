@@ -24,7 +24,7 @@ EXPORTS = (
     "xeng_samples_since_dump", "xeng_max_dump_samples", "xeng_plan_describe",
     "xeng_strerror", "xeng_last_error",
     "xeng_stream_create", "xeng_stream_next_slot", "xeng_stream_push", "xeng_stream_dump_wait",
-    "xeng_stream_gulp_times", "xeng_stream_gulps", "xeng_stream_destroy",
+    "xeng_stream_gulp_times", "xeng_stream_gulps", "xeng_stream_backlog", "xeng_stream_destroy",
     "xeng_autotune", "xeng_graph_create", "xeng_graph_launch", "xeng_graph_destroy",
     "xeng_set_fast_autos", "xeng_dump_fast_autos",
     "xeng_ingest_create", "xeng_ingest_packet_stride", "xeng_ingest_gulp", "xeng_ingest_stats_get",
@@ -112,6 +112,8 @@ def load():
     lib.xeng_stream_gulp_times.restype = i32
     lib.xeng_stream_gulps.argtypes = [vp, ctypes.POINTER(i64)]
     lib.xeng_stream_gulps.restype = i32
+    lib.xeng_stream_backlog.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.xeng_stream_backlog.restype = i32
     lib.xeng_stream_destroy.argtypes = [vp]
     lib.xeng_stream_destroy.restype = i32
     lib.xeng_ingest_create.argtypes = [ctypes.POINTER(Subarray), ctypes.POINTER(PacketFormat),
@@ -374,6 +376,12 @@ class Stream:
     def gulps(self) -> int:
         v = ctypes.c_int64()
         _check(self._lib.xeng_stream_gulps(self._s, ctypes.byref(v)))
+        return v.value
+
+    def backlog(self) -> int:
+        """Gulps pushed whose integration has not finished on the device."""
+        v = ctypes.c_int64()
+        _check(self._lib.xeng_stream_backlog(self._s, ctypes.byref(v)))
         return v.value
 
     def close(self):

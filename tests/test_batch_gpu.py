@@ -93,36 +93,29 @@ def test_autotune_choices_stay_exact_and_are_cached(torch_cuda, oracle_lib):
         assert [s["kernel"] for s in c2.plan()["subarrays"]] == \
             [s["kernel"] for s in plan["subarrays"]]
 
-
-def test_batch_configuration_sampled(torch_cuda, oracle_lib):
-    # the five-subarray batch (N = 64 ... 2048, 4096 samples): autotuned,
-    # captured, replayed twice; sampled channels of every subarray checked
+def test_graph_survives_autotune(torch_cuda, oracle_lib):
+    # autotuning replans the context (new tile lists); a graph captured before
+    # keeps the lists it was captured with and still replays exactly
     from paper_1411_3751_amd import Correlator
     torch = torch_cuda
-    print("case batch configuration", flush=True)
-    streams, subs = [], []
-    for s in range(len(synth.BATCH_SHAPES)):
-        x, _, _, meta = synth.workload("batch", subarray=s)
-        streams.append(x)
-        subs.append(dict(n_inputs=meta["n_inputs"], n_chans=meta["n_chans"], n_time=meta["n_time"]))
-    dev = [torch.from_numpy(x).cuda() for x in streams]
-    out = [torch.empty((d["n_chans"], d["n_inputs"] * (d["n_inputs"] + 1) // 2, 2),
-                       dtype=torch.int32, device="cuda") for d in subs]
-    rng = np.random.default_rng(33)
+    print("case graph then autotune", flush=True)
+    rng = np.random.default_rng(34)
+    shapes = [(64, 8, 512), (128, 4, 300)]
+    subs = [dict(n_inputs=N, n_chans=F, n_time=T) for (N, F, T) in shapes]
+    dev = [torch.empty((T, F, N), dtype=torch.uint8, device="cuda") for (N, F, T) in shapes]
+    out = [torch.empty((F, N * (N + 1) // 2, 2), dtype=torch.int32, device="cuda")
+           for (N, F, T) in shapes]
     with Correlator(subs) as c:
-        c.autotune(dev, reps=2)
-        print("plan", c.plan(), flush=True)
         with c.capture(dev, out) as g:
-            for _ in range(2):
-                g.launch()
+            host = [rand4(rng, T, F, N) for (N, F, T) in shapes]
+            for d, h in zip(dev, host):
+                d.copy_(torch.from_numpy(h))
             torch.cuda.synchronize()
-    for x, d, o in zip(streams, subs, out):
-        N, F = d["n_inputs"], d["n_chans"]
-        got = o.cpu().numpy()
-        n_full = {64: F, 256: 8, 512: 4, 1024: 2, 2048: 1}[N]
-        chans = sorted(rng.choice(F, n_full, replace=False).tolist())
-        want = oracle_lib.narrow(oracle_lib.correlate(x, 4, chans=chans))
-        assert np.array_equal(got[chans], want), N
-        for f in rng.choice([f for f in range(F) if f not in chans] or [0], 3):
-            w = rng.integers(-4, 5, size=(N, 2)).astype(np.int64)
-            assert oracle_lib.projection_check(x, 4, int(f), got[f], w) == 0, (N, f)
+            c.autotune(dev, reps=1)
+            torch.cuda.synchronize()
+            for rep in range(2):
+                g.launch()
+                torch.cuda.synchronize()
+                for (N, F, T), h, o in zip(shapes, host, out):
+                    want = oracle_lib.narrow(oracle_lib.correlate(h, 4))
+                    assert np.array_equal(o.cpu().numpy(), want), (rep, N)
