@@ -28,10 +28,12 @@ PEAK_HBM_GBS = 8000.0            # MI355X HBM3E, GB/s
 CHANNEL_HZ = 24.0e3              # channel width of the paper's F-engine (Section 2)
 
 
-KERNEL = "xcorr_wg_kernel"        # the dominant kernel of a step
+KERNEL = "xcorr_w1_kernel"        # the dominant kernel of a step
 PROFILES = os.path.join(ROOT, "profiles")
+# device code the traffic counters depend on (the kernel and the helpers it
+# uses); host-only changes elsewhere do not invalidate them
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1411_3751_amd", "csrc", f)
-                  for f in ("xeng.hip", "xcorr_wg.h", "xcorr_i8.h")]
+                  for f in ("xcorr_w1.h", "xcorr_wg.h", "xcorr_i8.h")]
 
 
 def kernel_source_hash(files=None) -> str:
@@ -788,8 +790,7 @@ def xengine_bench(args):
     log("plan:", json.dumps(plan))
 
     def step():
-        corr.correlate([d_samples])
-        corr.dump([out], reset=True)
+        corr.correlate_dump([d_samples], [out])
 
     # settle: under sustained MFMA load the clock first overshoots downwards
     # and recovers over the next tens of milliseconds; a fixed stretch of
@@ -815,14 +816,20 @@ def xengine_bench(args):
     ms_step = t_start.elapsed_time(t_end) / n
 
     # kernel pass (after the timed region): an event pair on the stream
-    # around each correlate call times that launch of the tile kernel
+    # around each correlate call times that launch of the tile kernel (with
+    # the one-wave kernel the step is that one launch, the dump fused in)
     k_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
             for _ in range(n)]
+    fused = plan["subarrays"][0]["kernel"] == "one_wave"
     for k in range(n):
         k_ev[k][0].record(stream)
-        corr.correlate([d_samples])
+        if fused:
+            corr.correlate_dump([d_samples], [out])
+        else:
+            corr.correlate([d_samples])
         k_ev[k][1].record(stream)
-        corr.dump([out], reset=True)
+        if not fused:
+            corr.dump([out], reset=True)
     torch.cuda.synchronize()
     k_ms = [a.elapsed_time(b) for a, b in k_ev]
     ms_kernel = sum(k_ms) / n
@@ -851,7 +858,7 @@ def xengine_bench(args):
         "data": "synthetic",
         "config": {"workload": name, "n_inputs": N, "n_chans": F, "n_time": T,
                    "in_bits": in_bits, "engine": engine, "autotuned": bool(args.autotune),
-                   "step": "correlate + dump (device, reset)",
+                   "step": "correlate + dump (device, reset) in one xeng_correlate_dump call",
                    "kernel": plan["subarrays"][0]["kernel"]},
         "settle_steps": settle_steps,
         "settle_s": args.settle_s,

@@ -110,6 +110,17 @@ int xeng_correlate(xeng_ctx *ctx, const void *const *d_samples);
  */
 int xeng_dump(xeng_ctx *ctx, void *const *out, int out_is_device, int reset);
 
+/*
+ * xeng_correlate(ctx, d_samples) followed by xeng_dump(ctx, out, out_is_device,
+ * reset), with the same arguments, checks and results. With device outputs and
+ * reset != 0 the two are fused where the kernel allows it (4-bit input on the
+ * int8 engine): the last launch writes each subarray's final sums straight
+ * into out[s] instead of the accumulator, so the step reads the accumulator
+ * at most once and never writes it. Otherwise it is exactly the two calls.
+ */
+int xeng_correlate_dump(xeng_ctx *ctx, const void *const *d_samples, void *const *out,
+                        int out_is_device, int reset);
+
 /* Release the context and its device memory (waits for its stream). NULL is a no-op. */
 int xeng_destroy(xeng_ctx *ctx);
 

@@ -1,0 +1,448 @@
+// One-wave-per-SIMD X-engine kernel for 4-bit input (N a multiple of 16),
+// int8 MFMA with int32 accumulation.
+//
+// Work is a host-built list of half tiles of the lower block triangle of
+// V[f] = sum_t x(t, f) x(t, f)^H (Section 2.5; Fig. 2 caption), over 128 x 128
+// tiles (channel f, 128-input block I, block J <= I):
+//   - an off-diagonal tile (I > J) is two items, one per 64-input half h of
+//     its J block: 128 x 64 visibilities, 4 x 2 MFMA blocks of 32 x 32;
+//   - a diagonal tile (I = J) needs the 10 of its 16 blocks on or below the
+//     diagonal; they are split into two items of 5 blocks, part 0 =
+//     (0,0) (1,0) (2,0) (3,0) (1,1) and part 1 = (2,1) (3,1) (2,2) (3,2) (3,3)
+//     (x = I block, y = J block of 32 inputs), so no block above the diagonal
+//     is computed and both parts cost the same.
+// Each workgroup is one wave with up to 512 registers (the 8 accumulator
+// blocks alone take the 256 accumulation registers), so a SIMD holds one
+// wave and a CU four; every wave walks its own slice of the list.
+//
+// Staging: every wave owns a 6-deep LDS ring of 32-sample stages (one K step
+// of v_mfma_i32_32x32x32_i8). A stage is an I region (32 rows x 128 inputs)
+// and a J region (32 rows x the 64 inputs of the half), copied raw from HBM
+// by buffer loads that write LDS directly, 5 stages ahead of the one being
+// multiplied. Nothing is shared between waves, so there are no barriers: a
+// wave only waits for its own copies.
+//
+// Fragments: as in the persistent 4-wave kernel, ds_read_b64_tr_b8 turns the
+// time-major rows into the K-major operands (lane l: input l % 32, K group
+// l / 32); chunk c (16 inputs) of row tau of the I region sits in slot
+// c ^ (tau & 7), of the J region in slot c ^ 2 ((tau >> 2) & 1), so the 8 rows
+// a 16-lane group reads fall on distinct banks. The fragments of stage s + 1
+// are read while stage s is multiplied.
+//
+// Operands: re = w & 0xF0F0F0F0 and im = (w << 4) & 0xF0F0F0F0 are 16 x the
+// nibbles, so products are 256 x the true ones. The imaginary part uses
+// ~im = -im - 1 on the J side (so that -(-8) never has to fit in int8):
+//   accI = sum re_I ~im_J + im_I re_J = 256 (Im V_ij - S_i),  S_i = sum_t re_i,
+// and S_i is summed from the raw bytes by v_dot8_i32_i4 with weights 1 on the
+// real nibbles, so the flush writes the exact Im V_ij. Segments of at most
+// SEG_T samples keep 256 |sum| <= 2^30.
+//
+// Flush: each item adds its sums to `src` (the accumulator, when it holds an
+// earlier part of the integration) and writes `dst` (the accumulator, or the
+// caller's output for a correlate-and-dump), in the output layout
+// [F][N(N+1)/2][2].
+#pragma once
+
+#include <type_traits>
+
+#include "xcorr_wg.h"
+
+namespace xeng {
+
+constexpr int W1_TK = 32;                             // samples per stage (one K step)
+constexpr int W1_NBUF = 6;                            // stages in a wave's LDS ring
+constexpr int W1_AHEAD = W1_NBUF - 1;                 // stages copied ahead
+constexpr int W1_IROW = 128;                          // bytes per staged I row
+constexpr int W1_JROW = 64;                           // bytes per staged J row
+constexpr int W1_JBASE = W1_TK * W1_IROW;             // J region offset in a stage
+constexpr int W1_STAGE = W1_TK * (W1_IROW + W1_JROW); // 6144 bytes
+constexpr int W1_DMA = W1_STAGE / (64 * 16);          // 16-byte copies per lane per stage (6)
+constexpr int W1_WG_PER_CU = 4;                       // one wave per SIMD
+
+struct W1Sub {
+    const uint8_t *samples; // [T][F][N] packed 4+4-bit
+    const int32_t *src;     // sums to add ([F][tri(N)][2]), or null
+    int32_t *dst;           // where the flush writes ([F][tri(N)][2])
+    int64_t t_begin;        // first sample of this launch's segment
+    int32_t t_count;        // samples in this segment (1 .. SEG_T)
+    int32_t n_chans;
+    int32_t n_inputs;       // multiple of 16
+    int32_t pad;
+};
+
+// Item: cs = chan | sub << 24; ij = bi | bj << 12 | role << 24 with role 0, 1
+// = off-diagonal tile, J half 0 or 1; 2, 3 = diagonal tile, part 0 or 1.
+struct W1Args {
+    W1Sub subs[WG_MAX_SUBS];
+    const WgItem *items;
+    const int32_t *wg_begin; // [n_wg + 1] item ranges per workgroup
+};
+
+// Per-role geometry. Read block k is a 32-input block of the stage (region,
+// position); MFMA block b multiplies read block xr(b) (I side, rows) by read
+// block yr(b) (J side, columns) into output block (ox(b), oy(b)) of 32 x 32
+// relative to the item's origin.
+template <int R> struct W1Role;
+
+template <> struct W1Role<0> { // off-diagonal half tile: 128 I x 64 J
+    static constexpr int NRD = 6, NB = 8;
+    __device__ static constexpr bool jreg(int k) { return k >= 4; }
+    __device__ static constexpr int pos(int k) { return k < 4 ? 32 * k : 32 * (k - 4); }
+    __device__ static constexpr int xr(int b) { return b & 3; }
+    __device__ static constexpr int yr(int b) { return 4 + (b >> 2); }
+    __device__ static constexpr int ox(int b) { return b & 3; }
+    __device__ static constexpr int oy(int b) { return b >> 2; }
+    __device__ static constexpr bool as_i(int k) { return k < 4; }
+    __device__ static constexpr bool as_j(int k) { return k >= 4; }
+    __device__ static constexpr bool diag(int) { return false; }
+};
+
+template <> struct W1Role<1> { // diagonal part 0: (0,0) (1,0) (2,0) (3,0) (1,1)
+    static constexpr int NRD = 4, NB = 5;
+    __device__ static constexpr bool jreg(int) { return false; }
+    __device__ static constexpr int pos(int k) { return 32 * k; }
+    __device__ static constexpr int xr(int b) { return b < 4 ? b : 1; }
+    __device__ static constexpr int yr(int b) { return b < 4 ? 0 : 1; }
+    __device__ static constexpr int ox(int b) { return xr(b); }
+    __device__ static constexpr int oy(int b) { return yr(b); }
+    __device__ static constexpr bool as_i(int) { return true; }
+    __device__ static constexpr bool as_j(int k) { return k < 2; }
+    __device__ static constexpr bool diag(int b) { return b == 0 || b == 4; }
+};
+
+template <> struct W1Role<2> { // diagonal part 1: (2,1) (3,1) (2,2) (3,2) (3,3)
+    static constexpr int NRD = 3, NB = 5;  // read block k = input block k + 1
+    __device__ static constexpr bool jreg(int) { return false; }
+    __device__ static constexpr int pos(int k) { return 32 * (k + 1); }
+    __device__ static constexpr int ox(int b) { return (b == 0 || b == 2) ? 2 : 3; }
+    __device__ static constexpr int oy(int b) { return b < 2 ? 1 : (b < 4 ? 2 : 3); }
+    __device__ static constexpr int xr(int b) { return ox(b) - 1; }
+    __device__ static constexpr int yr(int b) { return oy(b) - 1; }
+    __device__ static constexpr bool as_i(int k) { return k >= 1; }
+    __device__ static constexpr bool as_j(int) { return true; }
+    __device__ static constexpr bool diag(int b) { return b == 2 || b == 4; }
+};
+
+// Wait until this wave's copies of every stage but the last `later` issued
+// have landed (each stage is W1_DMA copies).
+__device__ __forceinline__ void w1_wait_copies(int later)
+{
+    switch (later) {
+    case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+    case 1: asm volatile("s_waitcnt vmcnt(6)" ::: "memory"); break;
+    case 2: asm volatile("s_waitcnt vmcnt(12)" ::: "memory"); break;
+    case 3: asm volatile("s_waitcnt vmcnt(18)" ::: "memory"); break;
+    default: asm volatile("s_waitcnt vmcnt(24)" ::: "memory"); break;
+    }
+}
+
+// One K step of role R: unpack the raw fragments, sum the real parts of the
+// I-side rows, and issue the 4 NB MFMAs (all blocks' first product, then
+// all second products, ...: the same accumulator is reused 8 (or 5) MFMAs
+// later, never back to back).
+template <int R>
+__device__ __forceinline__ void w1_kstep(const i32x2 (&Rw)[W1Role<R>::NRD][2],
+                                         i32x16 (&accR)[W1Role<R>::NB],
+                                         i32x16 (&accI)[W1Role<R>::NB],
+                                         int32_t (&S)[W1Role<R>::NRD])
+{
+    typedef W1Role<R> Ro;
+    constexpr uint32_t M = 0xF0F0F0F0u;
+    i32x4 re[Ro::NRD], im[Ro::NRD], ni[Ro::NRD];
+#pragma unroll
+    for (int k = 0; k < Ro::NRD; ++k) {
+        const u32x4 p = {(uint32_t)Rw[k][0].x, (uint32_t)Rw[k][0].y, (uint32_t)Rw[k][1].x,
+                         (uint32_t)Rw[k][1].y};
+        re[k] = (i32x4)(p & M);
+        const u32x4 q = (p << 4) & M;
+        im[k] = (i32x4)q;
+        if (Ro::as_j(k)) ni[k] = (i32x4)(q ^ M);
+        if (Ro::as_i(k)) {
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+                S[k] = __builtin_amdgcn_sdot8((int)p[d], 0x10101010, S[k], false);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < Ro::NB; ++b)
+        accR[b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(re[Ro::xr(b)], re[Ro::yr(b)], accR[b], 0, 0, 0);
+#pragma unroll
+    for (int b = 0; b < Ro::NB; ++b)
+        accI[b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(re[Ro::xr(b)], ni[Ro::yr(b)], accI[b], 0, 0, 0);
+#pragma unroll
+    for (int b = 0; b < Ro::NB; ++b)
+        accR[b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(im[Ro::xr(b)], im[Ro::yr(b)], accR[b], 0, 0, 0);
+#pragma unroll
+    for (int b = 0; b < Ro::NB; ++b)
+        accI[b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(im[Ro::xr(b)], re[Ro::yr(b)], accI[b], 0, 0, 0);
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void xcorr_w1_kernel(W1Args a)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t lds[W1_NBUF * W1_STAGE];
+
+    const int lane = threadIdx.x;
+    typedef __attribute__((address_space(4))) const uint32_t c_u32_t;
+    typedef __attribute__((address_space(4))) const int32_t c_i32_t;
+    c_u32_t *itw = (c_u32_t *)a.items;
+    c_i32_t *wbeg = (c_i32_t *)a.wg_begin;
+    const int it_begin = __builtin_amdgcn_readfirstlane(wbeg[blockIdx.x]);
+    const int it_end = __builtin_amdgcn_readfirstlane(wbeg[blockIdx.x + 1]);
+    if (it_begin >= it_end) return;
+    auto item_at = [&](int it) {
+        const int u = __builtin_amdgcn_readfirstlane(it);
+        WgItem w;
+        w.cs = itw[2 * u];
+        w.ij = itw[2 * u + 1];
+        return w;
+    };
+    const uint32_t lds_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)lds;
+    constexpr uint32_t OOR = 0x80000000u;
+
+    // ---- copy cursor: every stage of every item of this wave, in order
+    int d_item = it_begin, d_stage = 0, d_nstage = 0, d_tcount = 0;
+    const uint8_t *d_base = nullptr;
+    uint32_t d_rowstride = 0;
+    uint32_t d_voff[W1_DMA];
+    // Lane-derived values are recomputed where they are used from an opaque
+    // copy of the lane index: hoisted out of the item loop, the three roles'
+    // offsets would not fit the registers left beside the accumulators.
+    auto fresh_lane = [&]() {
+        int l = lane;
+        asm volatile("" : "+v"(l));
+        return l;
+    };
+    auto d_setup = [&](int it) {
+        const int lane = fresh_lane();
+        const WgItem w = item_at(it);
+        const W1Sub &sb = a.subs[w.cs >> 24];
+        const int f = (int)(w.cs & 0xFFFFFFu);
+        const int bi = (int)(w.ij & 0xFFFu), bj = (int)((w.ij >> 12) & 0xFFFu);
+        const int role = (int)(w.ij >> 24);
+        const int N = sb.n_inputs;
+        d_rowstride = (uint32_t)sb.n_chans * (uint32_t)N;
+        d_tcount = sb.t_count;
+        d_nstage = (sb.t_count + W1_TK - 1) / W1_TK;
+        d_base = sb.samples + ((size_t)sb.t_begin * sb.n_chans + f) * (size_t)N;
+        // unit P = 64 u + lane of the stage: u < 4 in the I region (8 units
+        // per row), u >= 4 in the J region (4 units per row)
+#pragma unroll
+        for (int u = 0; u < W1_DMA; ++u) {
+            int tau, in;
+            bool on;
+            if (u < 4) {
+                tau = 8 * u + (lane >> 3);
+                const int c = (lane & 7) ^ (tau & 7);
+                in = 128 * bi + 16 * c;
+                on = in < N;
+            } else {
+                tau = 16 * (u - 4) + (lane >> 2);
+                const int c = (lane & 3) ^ (((tau >> 2) & 1) << 1);
+                in = 128 * bj + 64 * (role & 1) + 16 * c;
+                on = role < 2 && in < N; // diagonal items have no J region
+            }
+            d_voff[u] = on ? (uint32_t)tau * d_rowstride + (uint32_t)in : OOR;
+        }
+    };
+    int issued = 0, n_total = 0;
+    for (int it = it_begin; it < it_end; ++it) {
+        const W1Sub &sb = a.subs[item_at(it).cs >> 24];
+        n_total += (sb.t_count + W1_TK - 1) / W1_TK;
+    }
+    auto d_issue = [&]() {
+        const int t_first = d_stage * W1_TK;
+        const int nt = d_tcount - t_first < W1_TK ? d_tcount - t_first : W1_TK;
+        const uint64_t base = (uint64_t)(uintptr_t)(d_base + (size_t)t_first * d_rowstride);
+        const i32x4 rsrc = {(int)(uint32_t)base, (int)((uint32_t)(base >> 32) & 0xFFFFu),
+                            (int)((uint32_t)nt * d_rowstride), 0x00020000};
+        const uint32_t dst = lds_base + (uint32_t)((issued % W1_NBUF) * W1_STAGE);
+#pragma unroll
+        for (int u = 0; u < W1_DMA; ++u) dma16(rsrc, d_voff[u], dst + (uint32_t)(u * 1024));
+        ++issued;
+        if (++d_stage == d_nstage) {
+            d_stage = 0;
+            if (++d_item < it_end) d_setup(d_item);
+        }
+    };
+    d_setup(it_begin);
+#pragma unroll
+    for (int k = 0; k < W1_AHEAD; ++k)
+        if (issued < n_total) d_issue();
+
+    // Make stage s (of an item with t_count samples, stage index k within it)
+    // readable: this wave's copies of it have landed; rows past the end of
+    // the segment are cleared (their copies were out of range).
+    auto land = [&](int s, int k, int tcount) {
+        const int later = issued - (s + 1);
+        w1_wait_copies(later < 4 ? later : 4);
+        const int nt = tcount - k * W1_TK;
+        if (nt < W1_TK) {
+            const int lane = fresh_lane();
+            uint8_t *b = lds + (s % W1_NBUF) * W1_STAGE;
+#pragma unroll
+            for (int u = 0; u < W1_DMA; ++u) {
+                const int o = 1024 * u + 16 * lane;
+                const int row = o < W1_JBASE ? o / W1_IROW : (o - W1_JBASE) / W1_JROW;
+                if (row >= nt) *(u32x4 *)(b + o) = u32x4{0u, 0u, 0u, 0u};
+            }
+        }
+    };
+
+    int s = 0; // global index of the stage being multiplied
+
+    auto run = [&](auto role_c, const WgItem &w) {
+        constexpr int R = decltype(role_c)::value;
+        typedef W1Role<R> Ro;
+        const int lane = fresh_lane();
+        const int G = lane >> 4;
+        const W1Sub &sb = a.subs[w.cs >> 24];
+        const int f = (int)(w.cs & 0xFFFFFFu);
+        const int bi = (int)(w.ij & 0xFFFu), bj = (int)((w.ij >> 12) & 0xFFFu);
+        const int h = (int)(w.ij >> 24) & 1;
+        const int tcount = sb.t_count;
+        const int nst = (tcount + W1_TK - 1) / W1_TK;
+
+        // transposing-read offsets of this role's blocks within a stage
+        int fo[Ro::NRD];
+#pragma unroll
+        for (int k = 0; k < Ro::NRD; ++k) {
+            const int pos = Ro::pos(k) + 16 * (G & 1);
+            const int c = pos >> 4;
+            const int m = (lane >> 1) & 7, hh = lane & 1;
+            const int tau = 16 * (G >> 1) + m;
+            fo[k] = Ro::jreg(k) ? W1_JBASE + tau * W1_JROW + 16 * (c ^ (((tau >> 2) & 1) << 1)) + 8 * hh
+                                : tau * W1_IROW + 16 * (c ^ (tau & 7)) + 8 * hh;
+        }
+        auto read = [&](int slot, i32x2 (&Rw)[Ro::NRD][2]) {
+            const uint8_t *b = lds + slot * W1_STAGE;
+#pragma unroll
+            for (int k = 0; k < Ro::NRD; ++k)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    Rw[k][i] = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
+                        (lds_i32x2 *)(b + fo[k] + 8 * i * (Ro::jreg(k) ? W1_JROW : W1_IROW)));
+        };
+
+        i32x16 accR[Ro::NB], accI[Ro::NB];
+        int32_t S[Ro::NRD];
+#pragma unroll
+        for (int b = 0; b < Ro::NB; ++b) {
+            accR[b] = i32x16{};
+            accI[b] = i32x16{};
+        }
+#pragma unroll
+        for (int k = 0; k < Ro::NRD; ++k) S[k] = 0;
+
+        // two fragment buffers used in turn (no copies between K steps: a
+        // copy would make the compiler wait for the next stage's reads)
+        i32x2 Ra[Ro::NRD][2], Rb[Ro::NRD][2];
+        land(s, 0, tcount);
+        read(s % W1_NBUF, Ra);
+        auto step = [&](int k, i32x2 (&Rc)[Ro::NRD][2], i32x2 (&Rn)[Ro::NRD][2]) {
+            // the slot of stage s - 1 is free: its fragments were consumed by
+            // the previous K step
+            if (issued < n_total) d_issue();
+            // the reads are issued on every K step (the last one re-reads the
+            // current slot, unused) so that the LDS-counter waits the
+            // compiler places before the unpack count exactly these 2 NRD
+            // younger reads and never wait for them
+            const bool more = k + 1 < nst;
+            if (more) land(s + 1, k + 1, tcount);
+            read((more ? s + 1 : s) % W1_NBUF, Rn);
+            // issue them before this step's MFMAs (left alone, the scheduler
+            // sinks them to the end of the chain, and the next step waits)
+            __builtin_amdgcn_sched_barrier(0);
+            w1_kstep<R>(Rc, accR, accI, S);
+            ++s;
+        };
+        int k = 0;
+        for (; k + 1 < nst; k += 2) {
+            step(k, Ra, Rb);
+            step(k + 1, Rb, Ra);
+        }
+        if (k < nst) step(k, Ra, Rb);
+
+        // ---- flush. S: lanes l and l + 32 hold halves of the real-part sum
+        // of row l % 32 of read block k.
+#pragma unroll
+        for (int k = 0; k < Ro::NRD; ++k)
+            if (Ro::as_i(k)) S[k] += __shfl_xor(S[k], 32);
+        const int N = sb.n_inputs;
+        const int r0 = 128 * bi;
+        const int c0 = R == 0 ? 128 * bj + 64 * h : 128 * bi;
+        const int r1 = r0 + 128 < N ? r0 + 128 : N;
+        const int64_t tri = (int64_t)N * (N + 1) / 2;
+        const int64_t rb0 = (int64_t)r0 * (r0 + 1) / 2;
+        const int64_t rb1 = (int64_t)r1 * (r1 + 1) / 2;
+        const size_t cell0 = (size_t)f * (size_t)tri + (size_t)rb0;
+        const int nbytes = (int)((rb1 - rb0) * 8);
+        const __amdgpu_buffer_rsrc_t drs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)((uint2 *)sb.dst + cell0), (short)0, nbytes, 0x00020000);
+        const bool add = sb.src != nullptr;
+        const __amdgpu_buffer_rsrc_t srs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)((const uint2 *)(add ? sb.src : sb.dst) + cell0), (short)0, add ? nbytes : 0,
+            0x00020000);
+        const int lh = lane >> 5, lc = lane & 31;
+#pragma unroll
+        for (int b = 0; b < Ro::NB; ++b) {
+            // the block's sums stay in accumulation registers until here, so
+            // they are moved out one block at a time
+            asm volatile("" : "+a"(accR[b]), "+a"(accI[b]));
+#pragma unroll
+            for (int e0 = 0; e0 < 16; e0 += 4) {
+                // four elements at a time: keeps the scheduler from hoisting
+                // every block's loads (and their registers) to the top
+                __builtin_amdgcn_sched_barrier(0);
+                uint32_t off[4];
+                int32_t sv[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int rr = 8 * (e0 >> 2) + 4 * lh + e;
+                    const int i = r0 + 32 * Ro::ox(b) + rr;
+                    const int j = c0 + 32 * Ro::oy(b) + lc;
+                    const int rel = (int)((int64_t)i * (i + 1) / 2 - rb0);
+                    const bool ok = i < N && (!Ro::diag(b) || j <= i);
+                    off[e] = ok ? (uint32_t)(rel + j) * 8u : OOR;
+                    sv[e] = __shfl(S[Ro::xr(b)], rr);
+                }
+                u32x2 old[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    old[e] = add ? __builtin_amdgcn_raw_buffer_load_b64(srs, (int)off[e], 0, 0)
+                                 : u32x2{0u, 0u};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const u32x2 v = {old[e].x + (uint32_t)(accR[b][e0 + e] >> 8),
+                                     old[e].y + (uint32_t)((accI[b][e0 + e] >> 8) + sv[e])};
+                    __builtin_amdgcn_raw_buffer_store_b64(v, drs, (int)off[e], 0, 0);
+                }
+            }
+        }
+        // drain the flush (its stores may complete out of order with the copies)
+        dma_wait<0>();
+    };
+
+    for (int it = it_begin; it < it_end; ++it) {
+        const WgItem w = item_at(it);
+        const int role = (int)(w.ij >> 24);
+        if (role < 2) run(std::integral_constant<int, 0>(), w);
+        else if (role == 2) run(std::integral_constant<int, 1>(), w);
+        else run(std::integral_constant<int, 2>(), w);
+    }
+}
+
+// Plain copy of 8-byte cells (a dump of an accumulator that already holds
+// the output convention). Grid-stride, 16 bytes per thread per step.
+__global__ __launch_bounds__(256) void copy_cells_kernel(const uint4 *__restrict__ src,
+                                                         uint4 *__restrict__ dst, size_t n16,
+                                                         const uint2 *__restrict__ src_tail,
+                                                         uint2 *__restrict__ dst_tail, int tail)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += stride)
+        dst[k] = src[k];
+    if (blockIdx.x == 0 && threadIdx.x < tail) dst_tail[threadIdx.x] = src_tail[threadIdx.x];
+}
+
+} // namespace xeng

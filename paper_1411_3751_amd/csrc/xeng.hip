@@ -4,7 +4,12 @@
 // imaginary words hold Im V_ij - S_i, see xcorr_wg.h, and the dump kernel
 // turns them into Im V_ij), checks the exactness bounds before any launch,
 // splits each call into segments of at most SEG_T samples, and launches:
-//   - subarrays with N a multiple of 16 (4-bit) or 8 (8-bit): the
+//   - 4-bit subarrays with N a multiple of 16 on the int8 engine: the
+//     one-wave-per-SIMD kernel (xcorr_w1.h), all such subarrays in one launch
+//     over a precomputed, cost-balanced list of half tiles; its accumulator
+//     holds the output convention, and a correlate-and-dump writes the
+//     caller's output straight from the flush;
+//   - other subarrays with N a multiple of 16 (4-bit) or 8 (8-bit): the
 //     persistent-workgroup kernel, all such subarrays of one engine and input
 //     width in one launch over a precomputed, cost-balanced list of
 //     128 x 128 tiles;
@@ -30,6 +35,7 @@
 
 #include "../../include/xeng.h"
 #include "xcorr_i8.h"
+#include "xcorr_w1.h"
 #include "xcorr_wg.h"
 
 namespace {
@@ -66,7 +72,8 @@ struct Sub {
     int64_t since_dump = 0;    // samples accumulated since the last reset
     int64_t max_dump = 0;      // exactness bound on since_dump
     bool acc_zero = true;      // accumulator logically zero (next launch overwrites)
-    bool wave = false;         // handled by the persistent-workgroup kernel
+    bool wave = false;         // handled by a persistent kernel (one launch per group)
+    bool w1 = false;           // ... the one-wave kernel: accumulator in output convention
     int wt = 4;                // register kernel: wave tile edge in 16-row sub-blocks
     int bt = 128;              // register kernel: workgroup tile edge
     int n_tiles = 0;           // register kernel: tiles per channel
@@ -89,6 +96,7 @@ using DevBuf = std::shared_ptr<void>;
 struct WavePlan {
     int engine = XENG_ENGINE_I8;     // every subarray of a plan uses this engine
     int in_bits = 4;                 // and this input width
+    bool w1 = false;                 // one-wave kernel (half tiles) or 4-wave kernel (tiles)
     std::vector<int> subs;           // context subarray indices, in launch order
     std::vector<xeng::WgItem> items; // flat, grouped per workgroup
     std::vector<int32_t> wg_begin;   // [n_wg + 1]
@@ -138,6 +146,12 @@ KernelFn pick_kernel(int in_bits, int wt, int n_inputs)
 bool wave_path(const xeng_subarray &c)
 {
     return (c.in_bits == 4 && c.n_inputs % 16 == 0) || (c.in_bits == 8 && c.n_inputs % 8 == 0);
+}
+
+// One-wave kernel: 4-bit input, int8 engine, 16-byte copy chunks of whole inputs.
+bool w1_path(const xeng_subarray &c)
+{
+    return c.in_bits == 4 && c.engine == XENG_ENGINE_I8 && c.n_inputs % 16 == 0;
 }
 
 int choose_wt(int n_inputs)
@@ -194,7 +208,28 @@ void build_schedule(WavePlan &p, const std::vector<Sub> &subs, int n_cu, int wg_
         double cost;
     };
     std::vector<It> all;
-    for (size_t k = 0; k < p.subs.size(); ++k) {
+    for (size_t k = 0; k < p.subs.size() && p.w1; ++k) {
+        // one-wave kernel: off-diagonal tiles as two J halves (8 MFMA blocks
+        // per K step), diagonal tiles as two parts of 5 blocks
+        const Sub &s = subs[p.subs[k]];
+        const int nb = (s.cfg.n_inputs + 127) / 128;
+        const int nst = (s.cfg.n_time + xeng::W1_TK - 1) / xeng::W1_TK;
+        const int segs = (s.cfg.n_time + xeng::SEG_T - 1) / xeng::SEG_T;
+        const double per_seg = (double)nst / segs;
+        for (int f = 0; f < s.cfg.n_chans; ++f)
+            for (int bi = 0; bi < nb; ++bi)
+                for (int bj = 0; bj <= bi; ++bj)
+                    for (int r = 0; r < 2; ++r) {
+                        It it;
+                        it.w.cs = (uint32_t)f | ((uint32_t)k << 24);
+                        const uint32_t role = bi == bj ? 2u + (uint32_t)r : (uint32_t)r;
+                        it.w.ij = (uint32_t)bi | ((uint32_t)bj << 12) | (role << 24);
+                        // K steps times MFMA blocks, plus the flush
+                        it.cost = per_seg * (bi == bj ? 5.0 : 8.0) + 24.0;
+                        all.push_back(it);
+                    }
+    }
+    for (size_t k = 0; k < p.subs.size() && !p.w1; ++k) {
         const Sub &s = subs[p.subs[k]];
         const int nb = (s.cfg.n_inputs + 127) / 128;
         const int tks = s.cfg.in_bits == 4 ? xeng::WgGeom<4>::TKS : xeng::WgGeom<8>::TKS;
@@ -218,7 +253,8 @@ void build_schedule(WavePlan &p, const std::vector<Sub> &subs, int n_cu, int wg_
     if (order == 1)
         std::stable_sort(all.begin(), all.end(), [](const It &a, const It &b) { return a.cost > b.cost; });
     const int64_t n_items = (int64_t)all.size();
-    const int n_wg = (int)std::min<int64_t>((int64_t)n_cu * wg_per_cu, n_items);
+    const int per_cu = p.w1 ? xeng::W1_WG_PER_CU : wg_per_cu;
+    const int n_wg = (int)std::min<int64_t>((int64_t)n_cu * per_cu, n_items);
     p.n_wg = n_wg;
     std::vector<std::vector<int>> xwg(8);
     for (int b = 0; b < n_wg; ++b) xwg[b % 8].push_back(b);
@@ -315,10 +351,44 @@ int launch_regs(Sub &s, const void *d_samples, hipStream_t st)
     return XENG_OK;
 }
 
+// One-wave kernel. out == NULL: every segment integrates into the
+// accumulators. out != NULL (a correlate-and-dump with reset): the last
+// segment's flush writes subarray k's sums to out[k] instead, and the
+// accumulator is left as it was (the caller resets it).
+int launch_w1(xeng_ctx *ctx, WavePlan &p, const void *const *d_samples, void *const *out)
+{
+    const Sub &s0 = ctx->subs[p.subs[0]];
+    const int64_t T = s0.cfg.n_time;
+    for (int64_t t0 = 0; t0 < T; t0 += xeng::SEG_T) {
+        const bool last = t0 + xeng::SEG_T >= T;
+        xeng::W1Args a;
+        memset(&a, 0, sizeof a);
+        for (size_t k = 0; k < p.subs.size(); ++k) {
+            Sub &s = ctx->subs[p.subs[k]];
+            xeng::W1Sub &w = a.subs[k];
+            w.samples = (const uint8_t *)d_samples[p.subs[k]];
+            w.src = s.acc_zero ? nullptr : s.d_acc;
+            w.dst = (last && out) ? (int32_t *)out[p.subs[k]] : s.d_acc;
+            w.t_begin = t0;
+            w.t_count = (int32_t)std::min<int64_t>(s.cfg.n_time - t0, xeng::SEG_T);
+            w.n_chans = s.cfg.n_chans;
+            w.n_inputs = s.cfg.n_inputs;
+        }
+        a.items = p.d_items;
+        a.wg_begin = p.d_wg_begin;
+        hipLaunchKernelGGL(xeng::xcorr_w1_kernel, dim3(p.n_wg), dim3(64), 0, ctx->stream, a);
+        HIP_TRY(hipGetLastError());
+        if (!(last && out))
+            for (int k : p.subs) ctx->subs[k].acc_zero = false;
+    }
+    return XENG_OK;
+}
+
 // All subarrays of a plan have the same number of segments (a plan with
 // several subarrays is only built when every one fits in one segment).
 int launch_wave(xeng_ctx *ctx, WavePlan &p, const void *const *d_samples)
 {
+    if (p.w1) return launch_w1(ctx, p, d_samples, nullptr);
     const Sub &s0 = ctx->subs[p.subs[0]];
     const int64_t T = s0.cfg.n_time;
     for (int64_t t0 = 0; t0 < T; t0 += xeng::SEG_T) {
@@ -354,6 +424,19 @@ int launch_wave(xeng_ctx *ctx, WavePlan &p, const void *const *d_samples)
 
 int dump_device(const Sub &s, uint32_t *out, hipStream_t st)
 {
+    if (s.w1) {
+        // the accumulator already holds the output convention
+        const size_t cells = (size_t)s.tri * (size_t)s.cfg.n_chans;
+        const size_t n16 = cells / 2;
+        const int tail = (int)(cells % 2);
+        int blocks = (int)std::min<size_t>((n16 + 255) / 256, 8192);
+        if (blocks < 1) blocks = 1;
+        hipLaunchKernelGGL(xeng::copy_cells_kernel, dim3(blocks), dim3(256), 0, st,
+                           (const uint4 *)s.d_acc, (uint4 *)out, n16,
+                           (const uint2 *)s.d_acc + 2 * n16, (uint2 *)out + 2 * n16, tail);
+        HIP_TRY(hipGetLastError());
+        return XENG_OK;
+    }
     const unsigned gx = (unsigned)((s.tri + xeng::DUMP_PER_WG - 1) / xeng::DUMP_PER_WG);
     for (int c0 = 0; c0 < s.cfg.n_chans; c0 += 65535) {
         const int nc = std::min(65535, s.cfg.n_chans - c0);
@@ -377,13 +460,15 @@ int replan(xeng_ctx *ctx)
         const int nb = (s.cfg.n_inputs + s.bt - 1) / s.bt;
         s.n_tiles = nb * (nb + 1) / 2;
     }
-    const int kinds[3][2] = {{XENG_ENGINE_I8, 4}, {XENG_ENGINE_I8, 8}, {XENG_ENGINE_FP8, 4}};
+    // (engine, input width, one-wave kernel)
+    const int kinds[4][3] = {{XENG_ENGINE_I8, 4, 1}, {XENG_ENGINE_I8, 4, 0}, {XENG_ENGINE_I8, 8, 0},
+                             {XENG_ENGINE_FP8, 4, 0}};
     for (const auto &kd : kinds) {
         std::vector<int> es;
         bool one_group = true;
         for (int k = 0; k < (int)ctx->subs.size(); ++k) {
             const Sub &s = ctx->subs[k];
-            if (s.wave && s.cfg.engine == kd[0] && s.cfg.in_bits == kd[1]) {
+            if (s.wave && s.cfg.engine == kd[0] && s.cfg.in_bits == kd[1] && (int)s.w1 == kd[2]) {
                 es.push_back(k);
                 if (s.cfg.n_time > xeng::SEG_T) one_group = false;
             }
@@ -397,6 +482,7 @@ int replan(xeng_ctx *ctx)
             ctx->plans.emplace_back();
             ctx->plans.back().engine = kd[0];
             ctx->plans.back().in_bits = kd[1];
+            ctx->plans.back().w1 = kd[2] != 0;
             ctx->plans.back().subs = g;
         }
     }
@@ -417,8 +503,11 @@ struct SubKey {
         return std::tie(n, f, t, b, e) < std::tie(o.n, o.f, o.t, o.b, o.e);
     }
 };
+// Kernel families: register-staging tiles, the persistent 4-wave kernel, the
+// one-wave kernel.
+constexpr int FAM_REG = 0, FAM_WG = 1, FAM_W1 = 2;
 struct SubChoice {
-    bool wave;
+    int fam;
     int wt;
 };
 struct SchedChoice {
@@ -439,13 +528,21 @@ std::vector<SubKey> keys_of(const xeng_ctx *ctx)
     return v;
 }
 
-void set_choice(Sub &s, bool wave, int wt)
+// The best family a subarray can take: fam, or the next one down that
+// supports its shape and engine (the FP8 engine exists only in the 4-wave
+// kernel).
+void set_choice(Sub &s, int fam, int wt)
 {
-    // the FP8 engine exists only in the persistent kernel
-    s.wave = wave_path(s.cfg) && (wave || s.cfg.engine == XENG_ENGINE_FP8);
+    if (s.cfg.engine == XENG_ENGINE_FP8) fam = FAM_WG;
+    if (fam == FAM_W1 && !w1_path(s.cfg)) fam = FAM_WG;
+    if (fam == FAM_WG && !wave_path(s.cfg)) fam = FAM_REG;
+    s.wave = fam != FAM_REG;
+    s.w1 = fam == FAM_W1;
     s.wt = wt;
     s.bt = 32 * wt;
 }
+
+int fam_of(const Sub &s) { return s.w1 ? FAM_W1 : (s.wave ? FAM_WG : FAM_REG); }
 
 void apply_tuning_cache(xeng_ctx *ctx)
 {
@@ -454,7 +551,7 @@ void apply_tuning_cache(xeng_ctx *ctx)
     auto set_it = g_tune_set.find(keys_of(ctx));
     if (set_it != g_tune_set.end()) {
         for (size_t k = 0; k < ctx->subs.size(); ++k)
-            set_choice(ctx->subs[k], set_it->second[k].wave, set_it->second[k].wt);
+            set_choice(ctx->subs[k], set_it->second[k].fam, set_it->second[k].wt);
     } else {
         for (Sub &s : ctx->subs) {
             auto it = g_tune_sub.find(key_of(s.cfg));
@@ -462,7 +559,7 @@ void apply_tuning_cache(xeng_ctx *ctx)
                 all = false;
                 continue;
             }
-            set_choice(s, it->second.wave, it->second.wt);
+            set_choice(s, it->second.fam, it->second.wt);
         }
     }
     auto it = g_tune_sched.find(keys_of(ctx));
@@ -574,7 +671,7 @@ int xeng_create(const xeng_subarray *subs, int n_subs, void *hip_stream, xeng_ct
         s.cfg = subs[k];
         s.tri = (int64_t)s.cfg.n_inputs * (s.cfg.n_inputs + 1) / 2;
         s.max_dump = s.cfg.in_bits == 4 ? XENG_MAX_DUMP_SAMPLES_4BIT : XENG_MAX_DUMP_SAMPLES_8BIT;
-        set_choice(s, true, choose_wt(s.cfg.n_inputs));
+        set_choice(s, FAM_W1, choose_wt(s.cfg.n_inputs));
         const int nb = (s.cfg.n_inputs + s.bt - 1) / s.bt;
         s.n_tiles = nb * (nb + 1) / 2;
         const size_t bytes = (size_t)s.tri * (size_t)s.cfg.n_chans * 8;
@@ -692,6 +789,53 @@ int xeng_dump(xeng_ctx *ctx, void *const *out, int out_is_device, int reset)
     return XENG_OK;
 }
 
+int xeng_correlate_dump(xeng_ctx *ctx, const void *const *d_samples, void *const *out,
+                        int out_is_device, int reset)
+{
+    if (!ctx) return fail(XENG_EINVAL, "ctx is NULL");
+    if (!(out && out_is_device && reset)) {
+        // nothing to fuse: the two calls in order
+        int rc = xeng_correlate(ctx, d_samples);
+        if (rc) return rc;
+        return xeng_dump(ctx, out, out_is_device, reset);
+    }
+    if (!d_samples) return fail(XENG_EINVAL, "d_samples is NULL");
+    for (size_t k = 0; k < ctx->subs.size(); ++k) {
+        const Sub &s = ctx->subs[k];
+        if (!d_samples[k]) return fail(XENG_EINVAL, "d_samples[%zu] is NULL", k);
+        if (((uintptr_t)d_samples[k] & 15) != 0)
+            return fail(XENG_EINVAL, "d_samples[%zu] is not 16-byte aligned", k);
+        if (!out[k]) return fail(XENG_EINVAL, "out[%zu] is NULL", k);
+        if (s.since_dump + s.cfg.n_time > s.max_dump)
+            return fail(XENG_ERANGE,
+                        "subarray %zu: %lld + %d samples since the last dump would exceed the "
+                        "exactness bound %lld",
+                        k, (long long)s.since_dump, s.cfg.n_time, (long long)s.max_dump);
+    }
+    // one-wave groups write their last segment straight to out; the rest
+    // integrate and are dumped
+    for (WavePlan &p : ctx->plans) {
+        int rc = p.w1 ? launch_w1(ctx, p, d_samples, out) : launch_wave(ctx, p, d_samples);
+        if (rc) return rc;
+    }
+    for (size_t k = 0; k < ctx->subs.size(); ++k)
+        if (!ctx->subs[k].wave) {
+            int rc = launch_regs(ctx->subs[k], d_samples[k], ctx->stream);
+            if (rc) return rc;
+        }
+    for (size_t k = 0; k < ctx->subs.size(); ++k) {
+        Sub &s = ctx->subs[k];
+        if (s.w1) continue;
+        int rc = dump_device(s, (uint32_t *)out[k], ctx->stream);
+        if (rc) return rc;
+    }
+    for (Sub &s : ctx->subs) {
+        s.acc_zero = true;
+        s.since_dump = 0;
+    }
+    return XENG_OK;
+}
+
 int xeng_samples_since_dump(const xeng_ctx *ctx, int sub, int64_t *out)
 {
     if (!ctx || !out) return fail(XENG_EINVAL, "NULL argument");
@@ -721,10 +865,11 @@ int xeng_plan_describe(const xeng_ctx *ctx, char *buf, size_t len)
         if (s.wave)
             snprintf(item, sizeof item,
                      "%s{\"n_inputs\": %d, \"n_chans\": %d, \"n_time\": %d, \"in_bits\": %d, "
-                     "\"engine\": \"%s\", \"kernel\": \"persistent_workgroup\", \"tile\": 128, "
+                     "\"engine\": \"%s\", \"kernel\": \"%s\", \"tile\": 128, "
                      "\"launches_per_call\": %lld}",
                      k ? ", " : "", s.cfg.n_inputs, s.cfg.n_chans, s.cfg.n_time, s.cfg.in_bits,
-                     s.cfg.engine == XENG_ENGINE_I8 ? "i8" : "fp8", (long long)segs);
+                     s.cfg.engine == XENG_ENGINE_I8 ? "i8" : "fp8",
+                     s.w1 ? "one_wave" : "persistent_workgroup", (long long)segs);
         else
             snprintf(item, sizeof item,
                      "%s{\"n_inputs\": %d, \"n_chans\": %d, \"n_time\": %d, \"in_bits\": %d, "
@@ -744,8 +889,10 @@ int xeng_plan_describe(const xeng_ctx *ctx, char *buf, size_t len)
         const WavePlan &p = ctx->plans[q];
         char item[256];
         snprintf(item, sizeof item,
-                 "%s{\"subarrays\": %zu, \"items\": %zu, \"workgroups\": %d, \"balance\": %.4f}",
-                 q ? ", " : "", p.subs.size(), p.items.size(), p.n_wg,
+                 "%s{\"kernel\": \"%s\", \"subarrays\": %zu, \"items\": %zu, \"workgroups\": %d, "
+                 "\"balance\": %.4f}",
+                 q ? ", " : "", p.w1 ? "one_wave" : "persistent_workgroup", p.subs.size(),
+                 p.items.size(), p.n_wg,
                  p.max_wg_cost > 0 ? p.mean_wg_cost / p.max_wg_cost : 1.0);
         js += item;
     }

@@ -7,10 +7,10 @@
 //                   stream never waits, so the event marks the host's request)
 //   ingest stream : wait slot_free[slot] (gulp g - n_slots correlated),
 //                   caller's fill work, record ready[g]
-//   compute stream: wait ready[g], xeng_correlate, record slot_free[slot];
-//                   if g completes dump d: wait out_done[d % 2] (dump d - 2
-//                   copied out), xeng_dump into dump buffer d % 2 + reset,
-//                   record dumped[d % 2]; record done[g]
+//   compute stream: wait ready[g]; xeng_correlate, or, if g completes dump
+//                   d: wait out_done[d % 2] (dump d - 2 copied out), then
+//                   xeng_correlate_dump into dump buffer d % 2 with reset and
+//                   record dumped[d % 2]; record slot_free[slot] and done[g]
 //   output stream : wait dumped[d % 2], copy to host_dumps[d % n_host],
 //                   record out_done[d % 2]
 #pragma once
@@ -181,18 +181,18 @@ int xeng_stream_push(xeng_stream *s, int64_t *gulp)
     HIP_TRY(hipEventRecord(e.ready, s->s_in));
     HIP_TRY(hipStreamWaitEvent(s->s_comp, e.ready, 0));
     const void *p = s->ring + (size_t)slot * s->gulp_bytes;
-    int rc = xeng_correlate(s->ctx, &p);
-    if (rc) return rc;
-    HIP_TRY(hipEventRecord(s->slot_free[slot], s->s_comp));
-    s->slot_used[slot] = true;
+    int rc;
     if ((g + 1) % s->dump_every == 0) {
+        // the gulp that completes a dump period is correlated and dumped in
+        // one call (fused where the kernel allows it)
         const int64_t d = s->n_dumps;
         const int b = (int)(d % 2);
         // the buffer's previous dump (d - 2) must be copied out first
         if (s->out_pending[b]) HIP_TRY(hipStreamWaitEvent(s->s_comp, s->out_done[b], 0));
         void *outp = s->d_dump[b];
-        rc = xeng_dump(s->ctx, &outp, 1, 1);
+        rc = xeng_correlate_dump(s->ctx, &p, &outp, 1, 1);
         if (rc) return rc;
+        HIP_TRY(hipEventRecord(s->slot_free[slot], s->s_comp));
         HIP_TRY(hipEventRecord(s->dumped[b], s->s_comp));
         HIP_TRY(hipStreamWaitEvent(s->s_out, s->dumped[b], 0));
         if (!s->host.empty())
@@ -201,7 +201,12 @@ int xeng_stream_push(xeng_stream *s, int64_t *gulp)
         HIP_TRY(hipEventRecord(s->out_done[b], s->s_out));
         s->out_pending[b] = true;
         ++s->n_dumps;
+    } else {
+        rc = xeng_correlate(s->ctx, &p);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(s->slot_free[slot], s->s_comp));
     }
+    s->slot_used[slot] = true;
     HIP_TRY(hipEventRecord(e.done, s->s_comp));
     s->have_slot = false;
     ++s->n_pushed;
@@ -229,6 +234,7 @@ int xeng_stream_gulp_times(xeng_stream *s, int64_t g, float *arrive_ms, float *r
                     STREAM_HIST);
     GulpEv &e = s->ev[g % STREAM_HIST];
     HIP_TRY(hipEventSynchronize(e.done));
+    HIP_TRY(hipEventSynchronize(e.arrive));
     if (arrive_ms) HIP_TRY(hipEventElapsedTime(arrive_ms, e.arrive, e.done));
     if (ready_ms) HIP_TRY(hipEventElapsedTime(ready_ms, e.ready, e.done));
     return XENG_OK;

@@ -60,6 +60,7 @@ int time_one(xeng_ctx *ctx, int k, const void *const *d_samples, int reps, float
     WavePlan p;
     p.engine = s.cfg.engine;
     p.in_bits = s.cfg.in_bits;
+    p.w1 = s.w1;
     p.subs = {k};
     build_schedule(p, ctx->subs, ctx->n_cu, ctx->wg_per_cu, ctx->order);
     int rc = upload_plan(p);
@@ -107,20 +108,17 @@ int xeng_autotune(xeng_ctx *ctx, const void *const *d_samples, int reps)
     for (size_t k = 0; k < ctx->subs.size(); ++k) {
         Sub &s = ctx->subs[k];
         if (s.cfg.engine == XENG_ENGINE_FP8) continue; // one kernel family only
-        struct Cand {
-            bool wave;
-            int wt;
-        };
-        std::vector<Cand> cands;
-        if (wave_path(s.cfg)) cands.push_back({true, 4});
+        std::vector<SubChoice> cands;
+        if (w1_path(s.cfg)) cands.push_back({FAM_W1, 4});
+        if (wave_path(s.cfg)) cands.push_back({FAM_WG, 4});
         const int N = s.cfg.n_inputs;
-        if (N <= 128) cands.push_back({false, 1});
-        if (N <= 1024) cands.push_back({false, 2});
-        cands.push_back({false, 4});
+        if (N <= 128) cands.push_back({FAM_REG, 1});
+        if (N <= 1024) cands.push_back({FAM_REG, 2});
+        cands.push_back({FAM_REG, 4});
         float best = 0.f;
-        Cand pick = cands[0];
+        SubChoice pick = cands[0];
         for (size_t q = 0; q < cands.size(); ++q) {
-            set_choice(s, cands[q].wave, cands[q].wt);
+            set_choice(s, cands[q].fam, cands[q].wt);
             float ms = 0.f;
             int rc = time_one(ctx, (int)k, d_samples, reps, ms);
             if (rc) return rc;
@@ -129,11 +127,11 @@ int xeng_autotune(xeng_ctx *ctx, const void *const *d_samples, int reps)
                 pick = cands[q];
             }
         }
-        set_choice(s, pick.wave, pick.wt);
+        set_choice(s, pick.fam, pick.wt);
     }
     // the picks of each subarray timed alone (kept for contexts of that shape)
     std::vector<SubChoice> alone;
-    for (const Sub &s : ctx->subs) alone.push_back(SubChoice{s.wave, s.wt});
+    for (const Sub &s : ctx->subs) alone.push_back(SubChoice{fam_of(s), s.wt});
     // (2) schedule of the batched persistent launch, all subarrays together:
     // whole steps under each schedule option
     auto tune_schedule = [&](float &best, int &bw, int &bo) -> int {
@@ -169,7 +167,7 @@ int xeng_autotune(xeng_ctx *ctx, const void *const *d_samples, int reps)
     for (const Sub &s : ctx->subs) can_move |= wave_path(s.cfg) && !s.wave;
     if (ctx->subs.size() > 1 && can_move) {
         for (Sub &s : ctx->subs)
-            if (wave_path(s.cfg)) set_choice(s, true, s.wt);
+            if (wave_path(s.cfg)) set_choice(s, FAM_W1, s.wt);
         float best_all = 0.f;
         int bw_all = 2, bo_all = 0;
         rc = tune_schedule(best_all, bw_all, bo_all);
@@ -189,20 +187,20 @@ int xeng_autotune(xeng_ctx *ctx, const void *const *d_samples, int reps)
             ctx->order = bo;
             for (size_t k : order_n) {
                 Sub &s = ctx->subs[k];
-                if (alone[k].wave || !s.wave || s.cfg.engine == XENG_ENGINE_FP8) continue;
-                const int wt_now = s.wt;
-                set_choice(s, false, alone[k].wt);
+                if (alone[k].fam != FAM_REG || !s.wave || s.cfg.engine == XENG_ENGINE_FP8) continue;
+                const int wt_now = s.wt, fam_now = fam_of(s);
+                set_choice(s, FAM_REG, alone[k].wt);
                 rc = replan(ctx);
                 if (rc) return rc;
                 float ms = 0.f;
                 rc = time_runs(ctx, reps, [&]() { return launch_all(ctx, d_samples); }, ms);
                 if (rc) return rc;
                 if (ms < best) best = ms;
-                else set_choice(s, true, wt_now);
+                else set_choice(s, fam_now, wt_now);
             }
         } else {
             for (size_t k = 0; k < ctx->subs.size(); ++k)
-                set_choice(ctx->subs[k], alone[k].wave, alone[k].wt);
+                set_choice(ctx->subs[k], alone[k].fam, alone[k].wt);
         }
     }
     ctx->wg_per_cu = bw;
@@ -218,7 +216,7 @@ int xeng_autotune(xeng_ctx *ctx, const void *const *d_samples, int reps)
         std::lock_guard<std::mutex> lk(g_tune_mu);
         for (size_t k = 0; k < ctx->subs.size(); ++k) g_tune_sub[key_of(ctx->subs[k].cfg)] = alone[k];
         std::vector<SubChoice> chosen;
-        for (const Sub &s : ctx->subs) chosen.push_back(SubChoice{s.wave, s.wt});
+        for (const Sub &s : ctx->subs) chosen.push_back(SubChoice{fam_of(s), s.wt});
         g_tune_set[keys_of(ctx)] = chosen;
         g_tune_sched[keys_of(ctx)] = SchedChoice{bw, bo};
     }
@@ -246,8 +244,7 @@ int xeng_graph_create(xeng_ctx *ctx, const void *const *d_samples, void *const *
     if (e != hipSuccess) {
         rc = fail(XENG_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
     } else {
-        rc = xeng_correlate(ctx, d_samples);
-        if (!rc) rc = xeng_dump(ctx, out, 1, 1);
+        rc = xeng_correlate_dump(ctx, d_samples, out, 1, 1);
         e = hipStreamEndCapture(cap, &g);
         if (!rc && e != hipSuccess) rc = fail(XENG_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
     }

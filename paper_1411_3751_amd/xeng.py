@@ -20,7 +20,8 @@ MAX_DUMP_SAMPLES_8BIT = 65535
 MAX_CALL_SAMPLES_FP8 = 32768
 
 EXPORTS = (
-    "xeng_create", "xeng_correlate", "xeng_dump", "xeng_destroy", "xeng_set_stream",
+    "xeng_create", "xeng_correlate", "xeng_dump", "xeng_correlate_dump", "xeng_destroy",
+    "xeng_set_stream",
     "xeng_samples_since_dump", "xeng_max_dump_samples", "xeng_plan_describe",
     "xeng_strerror", "xeng_last_error",
     "xeng_stream_create", "xeng_stream_next_slot", "xeng_stream_push", "xeng_stream_dump_wait",
@@ -84,6 +85,8 @@ def load():
     lib.xeng_correlate.restype = i32
     lib.xeng_dump.argtypes = [vp, pp, i32, i32]
     lib.xeng_dump.restype = i32
+    lib.xeng_correlate_dump.argtypes = [vp, pp, pp, i32, i32]
+    lib.xeng_correlate_dump.restype = i32
     lib.xeng_destroy.argtypes = [vp]
     lib.xeng_destroy.restype = i32
     lib.xeng_set_stream.argtypes = [vp, vp]
@@ -250,6 +253,31 @@ class Correlator:
         _check(self._lib.xeng_graph_create(self._ctx, self._sample_ptrs(samples),
                                            _ptrs([o.data_ptr() for o in out]), ctypes.byref(g)))
         return Graph(self._lib, g, self)
+
+    def correlate_dump(self, samples, out=None, reset: bool = True, device: bool = True):
+        """correlate(samples) then dump(out, reset, device) in one call (fused
+        in the kernel where it can be); returns the list of outputs."""
+        out = self._outputs(out, device)
+        _check(self._lib.xeng_correlate_dump(self._ctx, self._sample_ptrs(samples),
+                                             _ptrs([o.data_ptr() for o in out]),
+                                             1 if device else 0, 1 if reset else 0))
+        return out
+
+    def _outputs(self, out, device):
+        import torch
+        if out is None:
+            dev = torch.device("cuda", torch.cuda.current_device()) if device else torch.device("cpu")
+            return [torch.empty(self.vis_shape(k), dtype=torch.int32, device=dev,
+                                pin_memory=(not device))
+                    for k in range(len(self.subs))]
+        if not isinstance(out, (list, tuple)):
+            out = [out]
+        for k, o in enumerate(out):
+            if tuple(o.shape) != self.vis_shape(k) or o.dtype != torch.int32 or not o.is_contiguous():
+                raise ValueError("subarray %d: output must be contiguous int32 %s" % (k, self.vis_shape(k)))
+            if o.is_cuda != device:
+                raise ValueError("subarray %d: output device does not match device=%s" % (k, device))
+        return list(out)
 
     def dump(self, out=None, reset: bool = True, device: bool = True):
         """Copy the sums into out (allocated if None); returns the list of outputs."""

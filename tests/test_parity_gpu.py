@@ -180,3 +180,41 @@ def test_8bit_multi_segment(torch_cuda, oracle_lib):
     s = rand_stream(rng, 40000, 2, 24, 8)
     want = oracle_lib.narrow(oracle_lib.correlate(s, 8))
     assert np.array_equal(gpu_once(torch_cuda, s, 8), want)
+
+def test_correlate_dump_one_call(torch_cuda, oracle_lib):
+    # xeng_correlate_dump: fused into the last launch for the one-wave kernel
+    # (the flush adds the accumulator of earlier calls and writes the output),
+    # plain correlate + dump for the other kernels; every result exact, the
+    # context reset after each call
+    from paper_1411_3751_amd import Correlator
+    torch = torch_cuda
+    print("case correlate_dump", flush=True)
+    rng = np.random.default_rng(41)
+    shapes = [(144, 3, 200, 4), (48, 2, 70000, 4), (40, 2, 90, 8), (37, 2, 120, 4)]
+    subs = [dict(n_inputs=N, n_chans=F, n_time=T, in_bits=b) for (N, F, T, b) in shapes]
+    a = [rand_stream(rng, T, F, N, b) for (N, F, T, b) in shapes]
+    b_ = [rand_stream(rng, T, F, N, b) for (N, F, T, b) in shapes]
+    with Correlator(subs) as c:
+        kinds = [s["kernel"] for s in c.plan()["subarrays"]]
+        print("kernels", kinds, flush=True)
+        da = [torch.from_numpy(x).cuda() for x in a]
+        db = [torch.from_numpy(x).cuda() for x in b_]
+        # after an earlier call: sums of both
+        c.correlate(da)
+        outs = [o.cpu().numpy() for o in c.correlate_dump(db)]
+        for (N, F, T, bits), x, y, o in zip(shapes, a, b_, outs):
+            want = oracle_lib.narrow(oracle_lib.correlate(x, bits) + oracle_lib.correlate(y, bits))
+            assert np.array_equal(o, want), (N, T, bits)
+        assert c.samples_since_dump() == 0
+        # from a reset context: one call's sums
+        outs = [o.cpu().numpy() for o in c.correlate_dump(da)]
+        for (N, F, T, bits), x, o in zip(shapes, a, outs):
+            assert np.array_equal(o, oracle_lib.narrow(oracle_lib.correlate(x, bits))), (N, T, bits)
+        # without reset (not fused): a snapshot, then the integration goes on
+        outs = [o.cpu().numpy() for o in c.correlate_dump(db, reset=False)]
+        for (N, F, T, bits), y, o in zip(shapes, b_, outs):
+            assert np.array_equal(o, oracle_lib.narrow(oracle_lib.correlate(y, bits))), (N, T, bits)
+        outs = [o.cpu().numpy() for o in c.correlate_dump(da)]
+        for (N, F, T, bits), x, y, o in zip(shapes, a, b_, outs):
+            want = oracle_lib.narrow(oracle_lib.correlate(x, bits) + oracle_lib.correlate(y, bits))
+            assert np.array_equal(o, want), (N, T, bits)
