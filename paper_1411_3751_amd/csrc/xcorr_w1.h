@@ -1,33 +1,40 @@
-// One-wave-per-SIMD X-engine kernel for 4-bit input (N a multiple of 16),
-// int8 MFMA with int32 accumulation.
+// Wave-private X-engine kernels for 4-bit input (N a multiple of 16), int8
+// MFMA with int32 accumulation, in two shapes:
+//   V = 1: one wave per SIMD (up to 512 registers: 8 accumulator blocks of
+//          32 x 32, 256 accumulation registers), items of 128 x 64;
+//   V = 2: two waves per SIMD (256 registers each: 4 accumulator blocks),
+//          items of 64 x 64; the two waves of a SIMD fill each other's issue
+//          gaps around the matrix core.
 //
-// Work is a host-built list of half tiles of the lower block triangle of
-// V[f] = sum_t x(t, f) x(t, f)^H (Section 2.5; Fig. 2 caption), over 128 x 128
-// tiles (channel f, 128-input block I, block J <= I):
-//   - an off-diagonal tile (I > J) is two items, one per 64-input half h of
-//     its J block: 128 x 64 visibilities, 4 x 2 MFMA blocks of 32 x 32;
-//   - a diagonal tile (I = J) needs the 10 of its 16 blocks on or below the
-//     diagonal; they are split into two items of 5 blocks, part 0 =
+// Work is a host-built list of items of the lower block triangle of
+// V[f] = sum_t x(t, f) x(t, f)^H (Section 2.5; Fig. 2 caption), over square
+// tiles (channel f, input block I, block J <= I) of 128 (V = 1) or 64 (V = 2)
+// inputs:
+//   - V = 1: an off-diagonal tile is two items, one per 64-input half h of
+//     its J block (4 x 2 MFMA blocks); a diagonal tile's 10 blocks on or
+//     below the diagonal are split into two items of 5, part 0 =
 //     (0,0) (1,0) (2,0) (3,0) (1,1) and part 1 = (2,1) (3,1) (2,2) (3,2) (3,3)
-//     (x = I block, y = J block of 32 inputs), so no block above the diagonal
-//     is computed and both parts cost the same.
-// Each workgroup is one wave with up to 512 registers (the 8 accumulator
-// blocks alone take the 256 accumulation registers), so a SIMD holds one
-// wave and a CU four; every wave walks its own slice of the list.
+//     (x = I block, y = J block of 32 inputs);
+//   - V = 2: an off-diagonal tile is one item (2 x 2 blocks); a diagonal
+//     tile is one item of its 3 blocks (0,0) (1,0) (1,1).
+// No block above the diagonal is computed. Every workgroup is one wave and
+// walks its own slice of the list.
 //
-// Staging: every wave owns a 6-deep LDS ring of 32-sample stages (one K step
-// of v_mfma_i32_32x32x32_i8). A stage is an I region (32 rows x 128 inputs)
-// and a J region (32 rows x the 64 inputs of the half), copied raw from HBM
-// by buffer loads that write LDS directly, 5 stages ahead of the one being
-// multiplied. Nothing is shared between waves, so there are no barriers: a
-// wave only waits for its own copies.
+// Staging: every wave owns an LDS ring of 32-sample stages (one K step of
+// v_mfma_i32_32x32x32_i8). A stage is an I region (32 rows x the item's I
+// inputs) and a J region (32 rows x its J inputs), copied raw from HBM by
+// buffer loads that write LDS directly, NBUF - 1 stages ahead of the one
+// being multiplied. Nothing is shared between waves, so there are no
+// barriers: a wave only waits for its own copies. Copies are issued past the
+// end of the list too (out of range, no memory traffic), so every wait on
+// them is the same.
 //
 // Fragments: as in the persistent 4-wave kernel, ds_read_b64_tr_b8 turns the
 // time-major rows into the K-major operands (lane l: input l % 32, K group
-// l / 32); chunk c (16 inputs) of row tau of the I region sits in slot
-// c ^ (tau & 7), of the J region in slot c ^ 2 ((tau >> 2) & 1), so the 8 rows
-// a 16-lane group reads fall on distinct banks. The fragments of stage s + 1
-// are read while stage s is multiplied.
+// l / 32). Chunk c (16 inputs) of row tau sits in slot c ^ (tau & 7) of a
+// 128-byte row and in slot c ^ 2 ((tau >> 2) & 1) of a 64-byte row, so the 8
+// rows a 16-lane group reads fall on distinct banks. The fragments of stage
+// s + 1 are read while stage s is multiplied.
 //
 // Operands: re = w & 0xF0F0F0F0 and im = (w << 4) & 0xF0F0F0F0 are 16 x the
 // nibbles, so products are 256 x the true ones. The imaginary part uses
@@ -49,15 +56,36 @@
 
 namespace xeng {
 
-constexpr int W1_TK = 32;                             // samples per stage (one K step)
-constexpr int W1_NBUF = 6;                            // stages in a wave's LDS ring
-constexpr int W1_AHEAD = W1_NBUF - 1;                 // stages copied ahead
-constexpr int W1_IROW = 128;                          // bytes per staged I row
-constexpr int W1_JROW = 64;                           // bytes per staged J row
-constexpr int W1_JBASE = W1_TK * W1_IROW;             // J region offset in a stage
-constexpr int W1_STAGE = W1_TK * (W1_IROW + W1_JROW); // 6144 bytes
-constexpr int W1_DMA = W1_STAGE / (64 * 16);          // 16-byte copies per lane per stage (6)
-constexpr int W1_WG_PER_CU = 4;                       // one wave per SIMD
+constexpr int W1_TK = 32; // samples per stage (one K step)
+
+// Geometry of the two shapes (bytes per staged row are the input counts).
+template <int V> struct W1Geo;
+template <> struct W1Geo<1> {
+    static constexpr int IB = 128, JB = 64;   // staged I and J inputs
+    static constexpr int NBUF = 6;            // stages in a wave's ring
+    static constexpr int WG_PER_CU = 4;       // one wave per SIMD
+    static constexpr int TILE = 128;          // tile edge of the item list
+};
+template <> struct W1Geo<2> {
+    static constexpr int IB = 64, JB = 64;
+    static constexpr int NBUF = 4;
+    static constexpr int WG_PER_CU = 8;       // two waves per SIMD
+    static constexpr int TILE = 64;
+};
+template <int V> struct W1Layout {
+    typedef W1Geo<V> G;
+    static constexpr int JBASE = W1_TK * G::IB;            // J region offset in a stage
+    static constexpr int STAGE = W1_TK * (G::IB + G::JB);  // bytes per stage
+    static constexpr int DMA = STAGE / (64 * 16);          // 16-byte copies per lane per stage
+    static constexpr int IU = JBASE / (64 * 16);           // of which in the I region
+    static constexpr int AHEAD = G::NBUF - 1;              // stages copied ahead
+};
+
+// Slot of 16-byte chunk c in row tau of a region with `rowb`-byte rows.
+__device__ __forceinline__ constexpr int w1_slot(int rowb, int tau, int c)
+{
+    return rowb == 128 ? c ^ (tau & 7) : c ^ (((tau >> 2) & 1) << 1);
+}
 
 struct W1Sub {
     const uint8_t *samples; // [T][F][N] packed 4+4-bit
@@ -82,9 +110,9 @@ struct W1Args {
 // position); MFMA block b multiplies read block xr(b) (I side, rows) by read
 // block yr(b) (J side, columns) into output block (ox(b), oy(b)) of 32 x 32
 // relative to the item's origin.
-template <int R> struct W1Role;
+template <int V, int R> struct W1Role;
 
-template <> struct W1Role<0> { // off-diagonal half tile: 128 I x 64 J
+template <> struct W1Role<1, 0> { // off-diagonal half tile: 128 I x 64 J
     static constexpr int NRD = 6, NB = 8;
     __device__ static constexpr bool jreg(int k) { return k >= 4; }
     __device__ static constexpr int pos(int k) { return k < 4 ? 32 * k : 32 * (k - 4); }
@@ -97,7 +125,7 @@ template <> struct W1Role<0> { // off-diagonal half tile: 128 I x 64 J
     __device__ static constexpr bool diag(int) { return false; }
 };
 
-template <> struct W1Role<1> { // diagonal part 0: (0,0) (1,0) (2,0) (3,0) (1,1)
+template <> struct W1Role<1, 1> { // diagonal part 0: (0,0) (1,0) (2,0) (3,0) (1,1)
     static constexpr int NRD = 4, NB = 5;
     __device__ static constexpr bool jreg(int) { return false; }
     __device__ static constexpr int pos(int k) { return 32 * k; }
@@ -110,7 +138,7 @@ template <> struct W1Role<1> { // diagonal part 0: (0,0) (1,0) (2,0) (3,0) (1,1)
     __device__ static constexpr bool diag(int b) { return b == 0 || b == 4; }
 };
 
-template <> struct W1Role<2> { // diagonal part 1: (2,1) (3,1) (2,2) (3,2) (3,3)
+template <> struct W1Role<1, 2> { // diagonal part 1: (2,1) (3,1) (2,2) (3,2) (3,3)
     static constexpr int NRD = 3, NB = 5;  // read block k = input block k + 1
     __device__ static constexpr bool jreg(int) { return false; }
     __device__ static constexpr int pos(int k) { return 32 * (k + 1); }
@@ -123,30 +151,51 @@ template <> struct W1Role<2> { // diagonal part 1: (2,1) (3,1) (2,2) (3,2) (3,3)
     __device__ static constexpr bool diag(int b) { return b == 2 || b == 4; }
 };
 
-// Wait until this wave's copies of every stage but the last `later` issued
-// have landed (each stage is W1_DMA copies).
-__device__ __forceinline__ void w1_wait_copies(int later)
+template <> struct W1Role<2, 0> { // off-diagonal tile: 64 I x 64 J
+    static constexpr int NRD = 4, NB = 4;
+    __device__ static constexpr bool jreg(int k) { return k >= 2; }
+    __device__ static constexpr int pos(int k) { return 32 * (k & 1); }
+    __device__ static constexpr int xr(int b) { return b & 1; }
+    __device__ static constexpr int yr(int b) { return 2 + (b >> 1); }
+    __device__ static constexpr int ox(int b) { return b & 1; }
+    __device__ static constexpr int oy(int b) { return b >> 1; }
+    __device__ static constexpr bool as_i(int k) { return k < 2; }
+    __device__ static constexpr bool as_j(int k) { return k >= 2; }
+    __device__ static constexpr bool diag(int) { return false; }
+};
+
+template <> struct W1Role<2, 1> { // diagonal tile: (0,0) (1,0) (1,1)
+    static constexpr int NRD = 2, NB = 3;
+    __device__ static constexpr bool jreg(int) { return false; }
+    __device__ static constexpr int pos(int k) { return 32 * k; }
+    __device__ static constexpr int xr(int b) { return b == 0 ? 0 : 1; }
+    __device__ static constexpr int yr(int b) { return b == 2 ? 1 : 0; }
+    __device__ static constexpr int ox(int b) { return xr(b); }
+    __device__ static constexpr int oy(int b) { return yr(b); }
+    __device__ static constexpr bool as_i(int) { return true; }
+    __device__ static constexpr bool as_j(int) { return true; }
+    __device__ static constexpr bool diag(int b) { return b != 1; }
+};
+
+// Wait until at most N of this wave's vector-memory operations (copies) are
+// outstanding.
+template <int N>
+__device__ __forceinline__ void w1_wait_vm()
 {
-    switch (later) {
-    case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
-    case 1: asm volatile("s_waitcnt vmcnt(6)" ::: "memory"); break;
-    case 2: asm volatile("s_waitcnt vmcnt(12)" ::: "memory"); break;
-    case 3: asm volatile("s_waitcnt vmcnt(18)" ::: "memory"); break;
-    default: asm volatile("s_waitcnt vmcnt(24)" ::: "memory"); break;
-    }
+    asm volatile("s_waitcnt vmcnt(%0)" : : "n"(N) : "memory");
 }
 
 // One K step of role R: unpack the raw fragments, sum the real parts of the
 // I-side rows, and issue the 4 NB MFMAs (all blocks' first product, then
 // all second products, ...: the same accumulator is reused 8 (or 5) MFMAs
 // later, never back to back).
-template <int R>
-__device__ __forceinline__ void w1_kstep(const i32x2 (&Rw)[W1Role<R>::NRD][2],
-                                         i32x16 (&accR)[W1Role<R>::NB],
-                                         i32x16 (&accI)[W1Role<R>::NB],
-                                         int32_t (&S)[W1Role<R>::NRD])
+template <int V, int R>
+__device__ __forceinline__ void w1_kstep(const i32x2 (&Rw)[W1Role<V, R>::NRD][2],
+                                         i32x16 (&accR)[W1Role<V, R>::NB],
+                                         i32x16 (&accI)[W1Role<V, R>::NB],
+                                         int32_t (&S)[W1Role<V, R>::NRD])
 {
-    typedef W1Role<R> Ro;
+    typedef W1Role<V, R> Ro;
     constexpr uint32_t M = 0xF0F0F0F0u;
     i32x4 re[Ro::NRD], im[Ro::NRD], ni[Ro::NRD];
 #pragma unroll
@@ -177,10 +226,14 @@ __device__ __forceinline__ void w1_kstep(const i32x2 (&Rw)[W1Role<R>::NRD][2],
         accI[b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(im[Ro::xr(b)], re[Ro::yr(b)], accI[b], 0, 0, 0);
 }
 
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+// V = 1: one wave per SIMD; V = 2: two.
+template <int V>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(V, V)))
 void xcorr_w1_kernel(W1Args a)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[W1_NBUF * W1_STAGE];
+    typedef W1Geo<V> Geo;
+    typedef W1Layout<V> L;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[Geo::NBUF * L::STAGE];
 
     const int lane = threadIdx.x;
     typedef __attribute__((address_space(4))) const uint32_t c_u32_t;
@@ -200,19 +253,21 @@ void xcorr_w1_kernel(W1Args a)
     const uint32_t lds_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)lds;
     constexpr uint32_t OOR = 0x80000000u;
 
-    // ---- copy cursor: every stage of every item of this wave, in order
-    int d_item = it_begin, d_stage = 0, d_nstage = 0, d_tcount = 0;
-    const uint8_t *d_base = nullptr;
-    uint32_t d_rowstride = 0;
-    uint32_t d_voff[W1_DMA];
     // Lane-derived values are recomputed where they are used from an opaque
-    // copy of the lane index: hoisted out of the item loop, the three roles'
-    // offsets would not fit the registers left beside the accumulators.
+    // copy of the lane index: hoisted out of the item loop, every role's
+    // offsets would stay live beside the accumulators.
     auto fresh_lane = [&]() {
         int l = lane;
         asm volatile("" : "+v"(l));
         return l;
     };
+
+    // ---- copy cursor: every stage of every item of this wave, in order,
+    // then out-of-range copies (no memory traffic) for as long as asked
+    int d_item = it_begin, d_stage = 0, d_nstage = 0, d_tcount = 0;
+    const uint8_t *d_base = nullptr;
+    uint32_t d_rowstride = 0;
+    uint32_t d_voff[L::DMA];
     auto d_setup = [&](int it) {
         const int lane = fresh_lane();
         const WgItem w = item_at(it);
@@ -225,65 +280,62 @@ void xcorr_w1_kernel(W1Args a)
         d_tcount = sb.t_count;
         d_nstage = (sb.t_count + W1_TK - 1) / W1_TK;
         d_base = sb.samples + ((size_t)sb.t_begin * sb.n_chans + f) * (size_t)N;
-        // unit P = 64 u + lane of the stage: u < 4 in the I region (8 units
-        // per row), u >= 4 in the J region (4 units per row)
+        // unit 64 u + lane of the stage: u < IU in the I region, the rest in
+        // the J region (64-byte rows: 4 units per row)
 #pragma unroll
-        for (int u = 0; u < W1_DMA; ++u) {
+        for (int u = 0; u < L::DMA; ++u) {
             int tau, in;
             bool on;
-            if (u < 4) {
-                tau = 8 * u + (lane >> 3);
-                const int c = (lane & 7) ^ (tau & 7);
-                in = 128 * bi + 16 * c;
+            if (u < L::IU) {
+                constexpr int UPR = Geo::IB / 16; // units per I row
+                tau = (64 / UPR) * u + lane / UPR;
+                const int c = w1_slot(Geo::IB, tau, lane % UPR);
+                in = Geo::TILE * bi + 16 * c;
                 on = in < N;
             } else {
-                tau = 16 * (u - 4) + (lane >> 2);
-                const int c = (lane & 3) ^ (((tau >> 2) & 1) << 1);
-                in = 128 * bj + 64 * (role & 1) + 16 * c;
+                tau = 16 * (u - L::IU) + (lane >> 2);
+                const int c = w1_slot(64, tau, lane & 3);
+                in = Geo::TILE * bj + (V == 1 ? 64 * (role & 1) : 0) + 16 * c;
                 on = role < 2 && in < N; // diagonal items have no J region
             }
             d_voff[u] = on ? (uint32_t)tau * d_rowstride + (uint32_t)in : OOR;
         }
     };
-    int issued = 0, n_total = 0;
-    for (int it = it_begin; it < it_end; ++it) {
-        const W1Sub &sb = a.subs[item_at(it).cs >> 24];
-        n_total += (sb.t_count + W1_TK - 1) / W1_TK;
-    }
+    int issued = 0;
     auto d_issue = [&]() {
+        const bool live = d_item < it_end;
         const int t_first = d_stage * W1_TK;
         const int nt = d_tcount - t_first < W1_TK ? d_tcount - t_first : W1_TK;
         const uint64_t base = (uint64_t)(uintptr_t)(d_base + (size_t)t_first * d_rowstride);
         const i32x4 rsrc = {(int)(uint32_t)base, (int)((uint32_t)(base >> 32) & 0xFFFFu),
-                            (int)((uint32_t)nt * d_rowstride), 0x00020000};
-        const uint32_t dst = lds_base + (uint32_t)((issued % W1_NBUF) * W1_STAGE);
+                            live ? (int)((uint32_t)nt * d_rowstride) : 0, 0x00020000};
+        const uint32_t dst = lds_base + (uint32_t)((issued % Geo::NBUF) * L::STAGE);
 #pragma unroll
-        for (int u = 0; u < W1_DMA; ++u) dma16(rsrc, d_voff[u], dst + (uint32_t)(u * 1024));
+        for (int u = 0; u < L::DMA; ++u) dma16(rsrc, d_voff[u], dst + (uint32_t)(u * 1024));
         ++issued;
-        if (++d_stage == d_nstage) {
+        if (live && ++d_stage == d_nstage) {
             d_stage = 0;
             if (++d_item < it_end) d_setup(d_item);
         }
     };
     d_setup(it_begin);
 #pragma unroll
-    for (int k = 0; k < W1_AHEAD; ++k)
-        if (issued < n_total) d_issue();
+    for (int k = 0; k < L::AHEAD; ++k) d_issue();
 
-    // Make stage s (of an item with t_count samples, stage index k within it)
-    // readable: this wave's copies of it have landed; rows past the end of
-    // the segment are cleared (their copies were out of range).
+    // Make stage s (stage k of an item with tcount samples) readable: this
+    // wave's copies of it have landed (AHEAD - 1 later stages may still be in
+    // flight); rows past the end of the segment are cleared (their copies
+    // were out of range).
     auto land = [&](int s, int k, int tcount) {
-        const int later = issued - (s + 1);
-        w1_wait_copies(later < 4 ? later : 4);
+        w1_wait_vm<(L::AHEAD - 1) * L::DMA>();
         const int nt = tcount - k * W1_TK;
         if (nt < W1_TK) {
             const int lane = fresh_lane();
-            uint8_t *b = lds + (s % W1_NBUF) * W1_STAGE;
+            uint8_t *b = lds + (s % Geo::NBUF) * L::STAGE;
 #pragma unroll
-            for (int u = 0; u < W1_DMA; ++u) {
+            for (int u = 0; u < L::DMA; ++u) {
                 const int o = 1024 * u + 16 * lane;
-                const int row = o < W1_JBASE ? o / W1_IROW : (o - W1_JBASE) / W1_JROW;
+                const int row = o < L::JBASE ? o / Geo::IB : (o - L::JBASE) / Geo::JB;
                 if (row >= nt) *(u32x4 *)(b + o) = u32x4{0u, 0u, 0u, 0u};
             }
         }
@@ -293,7 +345,7 @@ void xcorr_w1_kernel(W1Args a)
 
     auto run = [&](auto role_c, const WgItem &w) {
         constexpr int R = decltype(role_c)::value;
-        typedef W1Role<R> Ro;
+        typedef W1Role<V, R> Ro;
         const int lane = fresh_lane();
         const int G = lane >> 4;
         const W1Sub &sb = a.subs[w.cs >> 24];
@@ -311,17 +363,17 @@ void xcorr_w1_kernel(W1Args a)
             const int c = pos >> 4;
             const int m = (lane >> 1) & 7, hh = lane & 1;
             const int tau = 16 * (G >> 1) + m;
-            fo[k] = Ro::jreg(k) ? W1_JBASE + tau * W1_JROW + 16 * (c ^ (((tau >> 2) & 1) << 1)) + 8 * hh
-                                : tau * W1_IROW + 16 * (c ^ (tau & 7)) + 8 * hh;
+            const int rowb = Ro::jreg(k) ? Geo::JB : Geo::IB;
+            fo[k] = (Ro::jreg(k) ? L::JBASE : 0) + tau * rowb + 16 * w1_slot(rowb, tau, c) + 8 * hh;
         }
         auto read = [&](int slot, i32x2 (&Rw)[Ro::NRD][2]) {
-            const uint8_t *b = lds + slot * W1_STAGE;
+            const uint8_t *b = lds + slot * L::STAGE;
 #pragma unroll
             for (int k = 0; k < Ro::NRD; ++k)
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
                     Rw[k][i] = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
-                        (lds_i32x2 *)(b + fo[k] + 8 * i * (Ro::jreg(k) ? W1_JROW : W1_IROW)));
+                        (lds_i32x2 *)(b + fo[k] + 8 * i * (Ro::jreg(k) ? Geo::JB : Geo::IB)));
         };
 
         i32x16 accR[Ro::NB], accI[Ro::NB];
@@ -338,22 +390,22 @@ void xcorr_w1_kernel(W1Args a)
         // copy would make the compiler wait for the next stage's reads)
         i32x2 Ra[Ro::NRD][2], Rb[Ro::NRD][2];
         land(s, 0, tcount);
-        read(s % W1_NBUF, Ra);
+        read(s % Geo::NBUF, Ra);
         auto step = [&](int k, i32x2 (&Rc)[Ro::NRD][2], i32x2 (&Rn)[Ro::NRD][2]) {
             // the slot of stage s - 1 is free: its fragments were consumed by
             // the previous K step
-            if (issued < n_total) d_issue();
+            d_issue();
             // the reads are issued on every K step (the last one re-reads the
             // current slot, unused) so that the LDS-counter waits the
             // compiler places before the unpack count exactly these 2 NRD
             // younger reads and never wait for them
             const bool more = k + 1 < nst;
             if (more) land(s + 1, k + 1, tcount);
-            read((more ? s + 1 : s) % W1_NBUF, Rn);
+            read((more ? s + 1 : s) % Geo::NBUF, Rn);
             // issue them before this step's MFMAs (left alone, the scheduler
             // sinks them to the end of the chain, and the next step waits)
             __builtin_amdgcn_sched_barrier(0);
-            w1_kstep<R>(Rc, accR, accI, S);
+            w1_kstep<V, R>(Rc, accR, accI, S);
             ++s;
         };
         int k = 0;
@@ -369,9 +421,9 @@ void xcorr_w1_kernel(W1Args a)
         for (int k = 0; k < Ro::NRD; ++k)
             if (Ro::as_i(k)) S[k] += __shfl_xor(S[k], 32);
         const int N = sb.n_inputs;
-        const int r0 = 128 * bi;
-        const int c0 = R == 0 ? 128 * bj + 64 * h : 128 * bi;
-        const int r1 = r0 + 128 < N ? r0 + 128 : N;
+        const int r0 = Geo::TILE * bi;
+        const int c0 = (V == 1 && R == 0) ? 128 * bj + 64 * h : (R == 0 ? Geo::TILE * bj : Geo::TILE * bi);
+        const int r1 = r0 + Geo::TILE < N ? r0 + Geo::TILE : N;
         const int64_t tri = (int64_t)N * (N + 1) / 2;
         const int64_t rb0 = (int64_t)r0 * (r0 + 1) / 2;
         const int64_t rb1 = (int64_t)r1 * (r1 + 1) / 2;
@@ -426,10 +478,17 @@ void xcorr_w1_kernel(W1Args a)
     for (int it = it_begin; it < it_end; ++it) {
         const WgItem w = item_at(it);
         const int role = (int)(w.ij >> 24);
-        if (role < 2) run(std::integral_constant<int, 0>(), w);
-        else if (role == 2) run(std::integral_constant<int, 1>(), w);
-        else run(std::integral_constant<int, 2>(), w);
+        if constexpr (V == 1) {
+            if (role < 2) run(std::integral_constant<int, 0>(), w);
+            else if (role == 2) run(std::integral_constant<int, 1>(), w);
+            else run(std::integral_constant<int, 2>(), w);
+        } else {
+            if (role < 2) run(std::integral_constant<int, 0>(), w);
+            else run(std::integral_constant<int, 1>(), w);
+        }
     }
+    // the copies issued past the end still land in this workgroup's LDS
+    dma_wait<0>();
 }
 
 // Plain copy of 8-byte cells (a dump of an accumulator that already holds

@@ -29,8 +29,13 @@
 //
 // Operands: re, im and ~im (= -im - 1, so that -(-8) or -(-128) never has to
 // fit in int8); 4-bit values are scaled by 16 by the nibble masks (see
-// xcorr_i8.h). Results go to the raw accumulator (Im holds Im V_ij - S_i with
-// S_i = sum_t re_i; the dump subtracts the diagonal).
+// xcorr_i8.h). The int8 engines' imaginary sums are then Im V_ij - S_i with
+// S_i = sum_t re_i; each wave also sums S_i for its rows (v_dot8_i32_i4 on
+// the raw 4-bit words with weight 1 on the real nibbles, v_dot4_i32_i8 on the
+// 8-bit real parts) and the flush adds it back, so every flush writes the
+// exact V_ij. A flush adds its sums to `src` (the accumulator, when it holds
+// an earlier part of the integration) and writes `dst` (the accumulator, or
+// the caller's output for a correlate-and-dump).
 #pragma once
 
 #include <type_traits>
@@ -84,12 +89,13 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 struct WgSub {
     const uint8_t *samples; // [T][F][N] packed 4+4-bit
-    int32_t *acc;           // [F][tri(N)][2] raw accumulator
+    const int32_t *src;     // sums to add ([F][tri(N)][2]), or null
+    int32_t *dst;           // where the flush writes ([F][tri(N)][2])
     int64_t t_begin;        // first sample of this launch's segment
     int32_t t_count;        // samples in this segment (<= SEG_T), > 0
     int32_t n_chans;
     int32_t n_inputs;       // multiple of 16
-    int32_t accumulate;     // 0: overwrite, 1: add
+    int32_t pad;
 };
 
 // Tile: chan | sub << 24, then bi | bj << 16 (128-input block indices).
@@ -136,13 +142,17 @@ __device__ __forceinline__ u32x4 wg_raw(const WgRaw &R, int k, int sd, int blk)
                  (uint32_t)R[k][sd][blk][1].x, (uint32_t)R[k][sd][blk][1].y};
 }
 
-__device__ __forceinline__ void wg_unpack(const WgRaw &R, int k, WgOps &o)
+// ... and S[x] += the real parts of its I-side words (row sums for the Im
+// correction): 4 v_dot8_i32_i4 with weights 1 on the real nibbles
+__device__ __forceinline__ void wg_unpack(const WgRaw &R, int k, WgOps &o, int32_t (&S)[2])
 {
 #pragma unroll
     for (int x = 0; x < 2; ++x) {
         const u32x4 p = wg_raw(R, k, 0, x);
         o.reI[x] = (i32x4)(p & 0xF0F0F0F0u);
         o.imI[x] = (i32x4)((p << 4) & 0xF0F0F0F0u);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) S[x] = __builtin_amdgcn_sdot8((int)p[d], 0x10101010, S[x], false);
     }
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
@@ -171,10 +181,14 @@ __device__ __forceinline__ void wg8_split(const WgRaw &R, int sd, int blk, i32x4
     }
 }
 
-__device__ __forceinline__ void wg8_unpack(const WgRaw &R, WgOps &o)
+__device__ __forceinline__ void wg8_unpack(const WgRaw &R, WgOps &o, int32_t (&S)[2])
 {
 #pragma unroll
-    for (int x = 0; x < 2; ++x) wg8_split(R, 0, x, o.reI[x], o.imI[x]);
+    for (int x = 0; x < 2; ++x) {
+        wg8_split(R, 0, x, o.reI[x], o.imI[x]);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) S[x] = __builtin_amdgcn_sdot4(o.reI[x][d], 0x01010101, S[x], false);
+    }
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
         wg8_split(R, 1, y, o.reJ[y], o.imJ[y]);
@@ -551,6 +565,7 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
                 accR[x][y] = AccT{};
                 accI[x][y] = AccT{};
             }
+        int32_t S[2] = {0, 0}; // this lane's part of S_i of rows l % 32 of I blocks 0, 1
         // the stage's fragments were read by the previous step (RA); unpack
         // and multiply, then publish and read the next stage
         // The stage's fragments were read by the previous step (RA). Once
@@ -573,11 +588,11 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
             } else {
                 if (write) {
                     if constexpr (IN_BITS == 4) {
-                        wg_unpack(RA, 0, O0);
+                        wg_unpack(RA, 0, O0, S);
                         wg_mfma(O0, accR, accI);
-                        wg_unpack(RA, 1, O0);
+                        wg_unpack(RA, 1, O0, S);
                     } else {
-                        wg8_unpack(RA, O0);
+                        wg8_unpack(RA, O0, S);
                     }
                     wg_mfma_blocks<0, wg_split<IN_BITS>()>(O0, accR, accI);
                 }
@@ -594,56 +609,68 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
         // 8 (r / 4) + 4 (l / 32) + r % 4. Buffer loads / stores relative to
         // row r0: elements above the diagonal, past N, or of a wave that
         // writes nothing get an out-of-range offset (loads read 0, stores are
-        // dropped), no branches.
+        // dropped), no branches. S: lanes l and l + 32 hold halves of the row
+        // sum of row l % 32 of I block x; the int8 engines add it to Im.
         const int N = sb.n_inputs;
-        const int lh = lane >> 5, lc = lane & 31;
+        // lane-derived flush offsets from an opaque copy of the lane index, so
+        // that they are not hoisted out of the tile loop (and kept live in
+        // registers across the stage loop)
+        int fl = lane;
+        asm volatile("" : "+v"(fl));
+        const int lh = fl >> 5, lc = fl & 31;
+        if constexpr (ENG == ENG_I8) {
+#pragma unroll
+            for (int x = 0; x < 2; ++x) S[x] += __shfl_xor(S[x], 32);
+        }
         const int64_t tri = (int64_t)N * (N + 1) / 2;
         const int r1 = r0 + 64 < N ? r0 + 64 : (r0 < N ? N : r0);
         const int64_t rb0 = (int64_t)r0 * (r0 + 1) / 2;
         const int64_t rb1 = (int64_t)r1 * (r1 + 1) / 2;
-        const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)((uint2 *)sb.acc + (size_t)f * (size_t)tri + (size_t)rb0), (short)0,
-            (int)((rb1 - rb0) * 8), 0x00020000);
+        const size_t cell0 = (size_t)f * (size_t)tri + (size_t)rb0;
+        const int nbytes = (int)((rb1 - rb0) * 8);
+        const __amdgpu_buffer_rsrc_t drs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)((uint2 *)sb.dst + cell0), (short)0, nbytes, 0x00020000);
+        const bool add = sb.src != nullptr;
+        const __amdgpu_buffer_rsrc_t srs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)((const uint2 *)(add ? sb.src : sb.dst) + cell0), (short)0, add ? nbytes : 0,
+            0x00020000);
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
+                // one group of rows at a time (keeps the scheduler from
+                // hoisting every group's loads and offsets)
+                __builtin_amdgcn_sched_barrier(0);
                 uint32_t off[4][2];
+                int32_t sv[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int i = r0 + 32 * x + 8 * q + 4 * lh + e;
+                    const int rr = 8 * q + 4 * lh + e;
+                    const int i = r0 + 32 * x + rr;
                     const int rel = (int)((int64_t)i * (i + 1) / 2 - rb0);
+                    sv[e] = ENG == ENG_I8 ? __shfl(S[x], rr) : 0;
 #pragma unroll
                     for (int y = 0; y < 2; ++y) {
                         const int j = c0 + 32 * y + lc;
                         off[e][y] = (write && i < N && j <= i) ? (uint32_t)(rel + j) * 8u : OOR;
                     }
                 }
-                if (sb.accumulate) {
-                    u32x2 old[4][2];
+                u32x2 old[4][2];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
+                for (int e = 0; e < 4; ++e)
 #pragma unroll
-                        for (int y = 0; y < 2; ++y)
-                            old[e][y] = __builtin_amdgcn_raw_buffer_load_b64(vrs, (int)off[e][y], 0, 0);
+                    for (int y = 0; y < 2; ++y)
+                        old[e][y] = add ? __builtin_amdgcn_raw_buffer_load_b64(srs, (int)off[e][y], 0, 0)
+                                        : u32x2{0u, 0u};
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
+                for (int e = 0; e < 4; ++e)
 #pragma unroll
-                        for (int y = 0; y < 2; ++y) {
-                            const u32x2 v = {old[e][y].x + acc_word<IN_BITS>(accR[x][y][4 * q + e]),
-                                             old[e][y].y + acc_word<IN_BITS>(accI[x][y][4 * q + e])};
-                            __builtin_amdgcn_raw_buffer_store_b64(v, vrs, (int)off[e][y], 0, 0);
-                        }
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-#pragma unroll
-                        for (int y = 0; y < 2; ++y) {
-                            const u32x2 v = {acc_word<IN_BITS>(accR[x][y][4 * q + e]),
-                                             acc_word<IN_BITS>(accI[x][y][4 * q + e])};
-                            __builtin_amdgcn_raw_buffer_store_b64(v, vrs, (int)off[e][y], 0, 0);
-                        }
-                }
+                    for (int y = 0; y < 2; ++y) {
+                        const u32x2 v = {old[e][y].x + acc_word<IN_BITS>(accR[x][y][4 * q + e]),
+                                         old[e][y].y + acc_word<IN_BITS>(accI[x][y][4 * q + e]) +
+                                             (uint32_t)sv[e]};
+                        __builtin_amdgcn_raw_buffer_store_b64(v, drs, (int)off[e][y], 0, 0);
+                    }
             }
         // drain the flush (stores may complete out of order with the copies)
         dma_wait<0>();

@@ -72,8 +72,10 @@ struct Sub {
     int64_t since_dump = 0;    // samples accumulated since the last reset
     int64_t max_dump = 0;      // exactness bound on since_dump
     bool acc_zero = true;      // accumulator logically zero (next launch overwrites)
-    bool wave = false;         // handled by a persistent kernel (one launch per group)
-    bool w1 = false;           // ... the one-wave kernel: accumulator in output convention
+    bool wave = false;         // handled by a persistent kernel (one launch per group); its
+                               // accumulator holds the output convention
+    bool w1 = false;           // ... a wave-private one
+    int wv = 0;                // which one: 1 (one wave per SIMD) or 2 (two)
     int wt = 4;                // register kernel: wave tile edge in 16-row sub-blocks
     int bt = 128;              // register kernel: workgroup tile edge
     int n_tiles = 0;           // register kernel: tiles per channel
@@ -96,7 +98,8 @@ using DevBuf = std::shared_ptr<void>;
 struct WavePlan {
     int engine = XENG_ENGINE_I8;     // every subarray of a plan uses this engine
     int in_bits = 4;                 // and this input width
-    bool w1 = false;                 // one-wave kernel (half tiles) or 4-wave kernel (tiles)
+    bool w1 = false;                 // wave-private kernel (items per wave) or 4-wave kernel (tiles)
+    int wv = 0;                      // wave-private kernel: 1 or 2 waves per SIMD
     std::vector<int> subs;           // context subarray indices, in launch order
     std::vector<xeng::WgItem> items; // flat, grouped per workgroup
     std::vector<int32_t> wg_begin;   // [n_wg + 1]
@@ -115,6 +118,7 @@ struct xeng_ctx {
     int wg_per_cu = WG_PER_CU;       // persistent launches: workgroups per CU
     int order = 0;                   // persistent schedule: 0 locality, 1 costliest first
     bool tuned = false;              // choices came from the autotuner (or its cache)
+    std::string tune_log;            // JSON objects of the last autotune's timings
     hipStream_t stream = nullptr;
     int device = 0;
     int n_cu = 0;
@@ -209,23 +213,28 @@ void build_schedule(WavePlan &p, const std::vector<Sub> &subs, int n_cu, int wg_
     };
     std::vector<It> all;
     for (size_t k = 0; k < p.subs.size() && p.w1; ++k) {
-        // one-wave kernel: off-diagonal tiles as two J halves (8 MFMA blocks
-        // per K step), diagonal tiles as two parts of 5 blocks
+        // wave-private kernels. One wave per SIMD: tiles of 128, an
+        // off-diagonal tile as two J halves (8 MFMA blocks per K step), a
+        // diagonal tile as two parts of 5 blocks. Two waves per SIMD: tiles
+        // of 64, one item each (4 blocks, or 3 on the diagonal).
         const Sub &s = subs[p.subs[k]];
-        const int nb = (s.cfg.n_inputs + 127) / 128;
+        const int tile = p.wv == 1 ? 128 : 64;
+        const int parts = p.wv == 1 ? 2 : 1;
+        const int nb = (s.cfg.n_inputs + tile - 1) / tile;
         const int nst = (s.cfg.n_time + xeng::W1_TK - 1) / xeng::W1_TK;
         const int segs = (s.cfg.n_time + xeng::SEG_T - 1) / xeng::SEG_T;
         const double per_seg = (double)nst / segs;
         for (int f = 0; f < s.cfg.n_chans; ++f)
             for (int bi = 0; bi < nb; ++bi)
                 for (int bj = 0; bj <= bi; ++bj)
-                    for (int r = 0; r < 2; ++r) {
+                    for (int r = 0; r < parts; ++r) {
                         It it;
                         it.w.cs = (uint32_t)f | ((uint32_t)k << 24);
                         const uint32_t role = bi == bj ? 2u + (uint32_t)r : (uint32_t)r;
                         it.w.ij = (uint32_t)bi | ((uint32_t)bj << 12) | (role << 24);
                         // K steps times MFMA blocks, plus the flush
-                        it.cost = per_seg * (bi == bj ? 5.0 : 8.0) + 24.0;
+                        const double blocks = p.wv == 1 ? (bi == bj ? 5.0 : 8.0) : (bi == bj ? 3.0 : 4.0);
+                        it.cost = per_seg * blocks + 3.0 * blocks;
                         all.push_back(it);
                     }
     }
@@ -253,7 +262,8 @@ void build_schedule(WavePlan &p, const std::vector<Sub> &subs, int n_cu, int wg_
     if (order == 1)
         std::stable_sort(all.begin(), all.end(), [](const It &a, const It &b) { return a.cost > b.cost; });
     const int64_t n_items = (int64_t)all.size();
-    const int per_cu = p.w1 ? xeng::W1_WG_PER_CU : wg_per_cu;
+    const int per_cu = p.w1 ? (p.wv == 1 ? xeng::W1Geo<1>::WG_PER_CU : xeng::W1Geo<2>::WG_PER_CU)
+                            : wg_per_cu;
     const int n_wg = (int)std::min<int64_t>((int64_t)n_cu * per_cu, n_items);
     p.n_wg = n_wg;
     std::vector<std::vector<int>> xwg(8);
@@ -376,7 +386,10 @@ int launch_w1(xeng_ctx *ctx, WavePlan &p, const void *const *d_samples, void *co
         }
         a.items = p.d_items;
         a.wg_begin = p.d_wg_begin;
-        hipLaunchKernelGGL(xeng::xcorr_w1_kernel, dim3(p.n_wg), dim3(64), 0, ctx->stream, a);
+        if (p.wv == 1)
+            hipLaunchKernelGGL(xeng::xcorr_w1_kernel<1>, dim3(p.n_wg), dim3(64), 0, ctx->stream, a);
+        else
+            hipLaunchKernelGGL(xeng::xcorr_w1_kernel<2>, dim3(p.n_wg), dim3(64), 0, ctx->stream, a);
         HIP_TRY(hipGetLastError());
         if (!(last && out))
             for (int k : p.subs) ctx->subs[k].acc_zero = false;
@@ -384,26 +397,31 @@ int launch_w1(xeng_ctx *ctx, WavePlan &p, const void *const *d_samples, void *co
     return XENG_OK;
 }
 
-// All subarrays of a plan have the same number of segments (a plan with
-// several subarrays is only built when every one fits in one segment).
-int launch_wave(xeng_ctx *ctx, WavePlan &p, const void *const *d_samples)
+// Persistent kernels (all subarrays of a plan have the same number of
+// segments: a plan with several subarrays is only built when every one fits
+// in one segment). out == NULL: every segment integrates into the
+// accumulators. out != NULL (a correlate-and-dump with reset): the last
+// segment's flush writes subarray k's sums to out[k] instead, and the
+// accumulator is left as it was (the caller resets it).
+int launch_wave(xeng_ctx *ctx, WavePlan &p, const void *const *d_samples, void *const *out = nullptr)
 {
-    if (p.w1) return launch_w1(ctx, p, d_samples, nullptr);
+    if (p.w1) return launch_w1(ctx, p, d_samples, out);
     const Sub &s0 = ctx->subs[p.subs[0]];
     const int64_t T = s0.cfg.n_time;
     for (int64_t t0 = 0; t0 < T; t0 += xeng::SEG_T) {
+        const bool last = t0 + xeng::SEG_T >= T;
         xeng::WgArgs a;
         memset(&a, 0, sizeof a);
         for (size_t k = 0; k < p.subs.size(); ++k) {
             Sub &s = ctx->subs[p.subs[k]];
             xeng::WgSub &w = a.subs[k];
             w.samples = (const uint8_t *)d_samples[p.subs[k]];
-            w.acc = s.d_acc;
+            w.src = s.acc_zero ? nullptr : s.d_acc;
+            w.dst = (last && out) ? (int32_t *)out[p.subs[k]] : s.d_acc;
             w.t_begin = t0;
             w.t_count = (int32_t)std::min<int64_t>(s.cfg.n_time - t0, xeng::SEG_T);
             w.n_chans = s.cfg.n_chans;
             w.n_inputs = s.cfg.n_inputs;
-            w.accumulate = s.acc_zero ? 0 : 1;
         }
         a.items = p.d_items;
         a.wg_begin = p.d_wg_begin;
@@ -417,14 +435,15 @@ int launch_wave(xeng_ctx *ctx, WavePlan &p, const void *const *d_samples)
             hipLaunchKernelGGL((xeng::xcorr_wg_kernel<xeng::ENG_I8, 8>), dim3(p.n_wg),
                                dim3(xeng::WG_THREADS), 0, ctx->stream, a);
         HIP_TRY(hipGetLastError());
-        for (int k : p.subs) ctx->subs[k].acc_zero = false;
+        if (!(last && out))
+            for (int k : p.subs) ctx->subs[k].acc_zero = false;
     }
     return XENG_OK;
 }
 
 int dump_device(const Sub &s, uint32_t *out, hipStream_t st)
 {
-    if (s.w1) {
+    if (s.wave) {
         // the accumulator already holds the output convention
         const size_t cells = (size_t)s.tri * (size_t)s.cfg.n_chans;
         const size_t n16 = cells / 2;
@@ -460,15 +479,15 @@ int replan(xeng_ctx *ctx)
         const int nb = (s.cfg.n_inputs + s.bt - 1) / s.bt;
         s.n_tiles = nb * (nb + 1) / 2;
     }
-    // (engine, input width, one-wave kernel)
-    const int kinds[4][3] = {{XENG_ENGINE_I8, 4, 1}, {XENG_ENGINE_I8, 4, 0}, {XENG_ENGINE_I8, 8, 0},
-                             {XENG_ENGINE_FP8, 4, 0}};
+    // (engine, input width, wave-private kernel variant)
+    const int kinds[5][3] = {{XENG_ENGINE_I8, 4, 1}, {XENG_ENGINE_I8, 4, 2}, {XENG_ENGINE_I8, 4, 0},
+                             {XENG_ENGINE_I8, 8, 0}, {XENG_ENGINE_FP8, 4, 0}};
     for (const auto &kd : kinds) {
         std::vector<int> es;
         bool one_group = true;
         for (int k = 0; k < (int)ctx->subs.size(); ++k) {
             const Sub &s = ctx->subs[k];
-            if (s.wave && s.cfg.engine == kd[0] && s.cfg.in_bits == kd[1] && (int)s.w1 == kd[2]) {
+            if (s.wave && s.cfg.engine == kd[0] && s.cfg.in_bits == kd[1] && s.wv == kd[2]) {
                 es.push_back(k);
                 if (s.cfg.n_time > xeng::SEG_T) one_group = false;
             }
@@ -483,6 +502,7 @@ int replan(xeng_ctx *ctx)
             ctx->plans.back().engine = kd[0];
             ctx->plans.back().in_bits = kd[1];
             ctx->plans.back().w1 = kd[2] != 0;
+            ctx->plans.back().wv = kd[2];
             ctx->plans.back().subs = g;
         }
     }
@@ -504,8 +524,8 @@ struct SubKey {
     }
 };
 // Kernel families: register-staging tiles, the persistent 4-wave kernel, the
-// one-wave kernel.
-constexpr int FAM_REG = 0, FAM_WG = 1, FAM_W1 = 2;
+// wave-private kernel with one or two waves per SIMD.
+constexpr int FAM_REG = 0, FAM_WG = 1, FAM_W1 = 2, FAM_W2 = 3;
 struct SubChoice {
     int fam;
     int wt;
@@ -534,15 +554,28 @@ std::vector<SubKey> keys_of(const xeng_ctx *ctx)
 void set_choice(Sub &s, int fam, int wt)
 {
     if (s.cfg.engine == XENG_ENGINE_FP8) fam = FAM_WG;
-    if (fam == FAM_W1 && !w1_path(s.cfg)) fam = FAM_WG;
+    if ((fam == FAM_W1 || fam == FAM_W2) && !w1_path(s.cfg)) fam = FAM_WG;
     if (fam == FAM_WG && !wave_path(s.cfg)) fam = FAM_REG;
     s.wave = fam != FAM_REG;
-    s.w1 = fam == FAM_W1;
+    s.w1 = fam == FAM_W1 || fam == FAM_W2;
+    s.wv = fam == FAM_W1 ? 1 : (fam == FAM_W2 ? 2 : 0);
     s.wt = wt;
     s.bt = 32 * wt;
+    // the register-staging launch's grid follows the tile size
+    const int nb = (s.cfg.n_inputs + s.bt - 1) / s.bt;
+    s.n_tiles = nb * (nb + 1) / 2;
 }
 
-int fam_of(const Sub &s) { return s.w1 ? FAM_W1 : (s.wave ? FAM_WG : FAM_REG); }
+const char *fam_name(int fam)
+{
+    return fam == FAM_W1 ? "one_wave"
+                         : (fam == FAM_W2 ? "two_wave" : (fam == FAM_WG ? "persistent_workgroup" : "register_staging"));
+}
+
+int fam_of(const Sub &s)
+{
+    return s.wv == 1 ? FAM_W1 : (s.wv == 2 ? FAM_W2 : (s.wave ? FAM_WG : FAM_REG));
+}
 
 void apply_tuning_cache(xeng_ctx *ctx)
 {
@@ -671,7 +704,7 @@ int xeng_create(const xeng_subarray *subs, int n_subs, void *hip_stream, xeng_ct
         s.cfg = subs[k];
         s.tri = (int64_t)s.cfg.n_inputs * (s.cfg.n_inputs + 1) / 2;
         s.max_dump = s.cfg.in_bits == 4 ? XENG_MAX_DUMP_SAMPLES_4BIT : XENG_MAX_DUMP_SAMPLES_8BIT;
-        set_choice(s, FAM_W1, choose_wt(s.cfg.n_inputs));
+        set_choice(s, FAM_WG, choose_wt(s.cfg.n_inputs));
         const int nb = (s.cfg.n_inputs + s.bt - 1) / s.bt;
         s.n_tiles = nb * (nb + 1) / 2;
         const size_t bytes = (size_t)s.tri * (size_t)s.cfg.n_chans * 8;
@@ -812,10 +845,10 @@ int xeng_correlate_dump(xeng_ctx *ctx, const void *const *d_samples, void *const
                         "exactness bound %lld",
                         k, (long long)s.since_dump, s.cfg.n_time, (long long)s.max_dump);
     }
-    // one-wave groups write their last segment straight to out; the rest
-    // integrate and are dumped
+    // the persistent kernels write their last segment straight to out; the
+    // register-staging kernel integrates and is dumped
     for (WavePlan &p : ctx->plans) {
-        int rc = p.w1 ? launch_w1(ctx, p, d_samples, out) : launch_wave(ctx, p, d_samples);
+        int rc = launch_wave(ctx, p, d_samples, out);
         if (rc) return rc;
     }
     for (size_t k = 0; k < ctx->subs.size(); ++k)
@@ -825,7 +858,7 @@ int xeng_correlate_dump(xeng_ctx *ctx, const void *const *d_samples, void *const
         }
     for (size_t k = 0; k < ctx->subs.size(); ++k) {
         Sub &s = ctx->subs[k];
-        if (s.w1) continue;
+        if (s.wave) continue;
         int rc = dump_device(s, (uint32_t *)out[k], ctx->stream);
         if (rc) return rc;
     }
@@ -865,11 +898,11 @@ int xeng_plan_describe(const xeng_ctx *ctx, char *buf, size_t len)
         if (s.wave)
             snprintf(item, sizeof item,
                      "%s{\"n_inputs\": %d, \"n_chans\": %d, \"n_time\": %d, \"in_bits\": %d, "
-                     "\"engine\": \"%s\", \"kernel\": \"%s\", \"tile\": 128, "
+                     "\"engine\": \"%s\", \"kernel\": \"%s\", \"tile\": %d, "
                      "\"launches_per_call\": %lld}",
                      k ? ", " : "", s.cfg.n_inputs, s.cfg.n_chans, s.cfg.n_time, s.cfg.in_bits,
-                     s.cfg.engine == XENG_ENGINE_I8 ? "i8" : "fp8",
-                     s.w1 ? "one_wave" : "persistent_workgroup", (long long)segs);
+                     s.cfg.engine == XENG_ENGINE_I8 ? "i8" : "fp8", fam_name(fam_of(s)),
+                     s.wv == 2 ? 64 : 128, (long long)segs);
         else
             snprintf(item, sizeof item,
                      "%s{\"n_inputs\": %d, \"n_chans\": %d, \"n_time\": %d, \"in_bits\": %d, "
@@ -891,12 +924,13 @@ int xeng_plan_describe(const xeng_ctx *ctx, char *buf, size_t len)
         snprintf(item, sizeof item,
                  "%s{\"kernel\": \"%s\", \"subarrays\": %zu, \"items\": %zu, \"workgroups\": %d, "
                  "\"balance\": %.4f}",
-                 q ? ", " : "", p.w1 ? "one_wave" : "persistent_workgroup", p.subs.size(),
+                 q ? ", " : "", p.wv == 1 ? "one_wave" : (p.wv == 2 ? "two_wave" : "persistent_workgroup"),
+                 p.subs.size(),
                  p.items.size(), p.n_wg,
                  p.max_wg_cost > 0 ? p.mean_wg_cost / p.max_wg_cost : 1.0);
         js += item;
     }
-    js += "]}";
+    js += "], \"tuning\": [" + ctx->tune_log + "]}";
     if (js.size() + 1 > len) return fail(XENG_EINVAL, "buffer of %zu bytes too small", len);
     memcpy(buf, js.c_str(), js.size() + 1);
     return XENG_OK;

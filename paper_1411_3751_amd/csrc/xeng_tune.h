@@ -51,6 +51,19 @@ int time_runs(xeng_ctx *ctx, int reps, Fn fn, float &ms)
     return XENG_OK;
 }
 
+// Append one JSON object to the context's record of the last autotune.
+void tune_note(xeng_ctx *ctx, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void tune_note(xeng_ctx *ctx, const char *fmt, ...)
+{
+    char buf[256];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (!ctx->tune_log.empty()) ctx->tune_log += ", ";
+    ctx->tune_log += buf;
+}
+
 // Milliseconds of one subarray's work alone under its current choice.
 int time_one(xeng_ctx *ctx, int k, const void *const *d_samples, int reps, float &ms)
 {
@@ -61,6 +74,7 @@ int time_one(xeng_ctx *ctx, int k, const void *const *d_samples, int reps, float
     p.engine = s.cfg.engine;
     p.in_bits = s.cfg.in_bits;
     p.w1 = s.w1;
+    p.wv = s.wv;
     p.subs = {k};
     build_schedule(p, ctx->subs, ctx->n_cu, ctx->wg_per_cu, ctx->order);
     int rc = upload_plan(p);
@@ -104,12 +118,16 @@ int xeng_autotune(xeng_ctx *ctx, const void *const *d_samples, int reps)
     if (reps < 1) reps = 1;
     if (reps > 100) reps = 100;
     HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->tune_log.clear();
     // (1) kernel family per subarray, each timed alone
     for (size_t k = 0; k < ctx->subs.size(); ++k) {
         Sub &s = ctx->subs[k];
         if (s.cfg.engine == XENG_ENGINE_FP8) continue; // one kernel family only
         std::vector<SubChoice> cands;
-        if (w1_path(s.cfg)) cands.push_back({FAM_W1, 4});
+        if (w1_path(s.cfg)) {
+            cands.push_back({FAM_W2, 4});
+            cands.push_back({FAM_W1, 4});
+        }
         if (wave_path(s.cfg)) cands.push_back({FAM_WG, 4});
         const int N = s.cfg.n_inputs;
         if (N <= 128) cands.push_back({FAM_REG, 1});
@@ -122,6 +140,10 @@ int xeng_autotune(xeng_ctx *ctx, const void *const *d_samples, int reps)
             float ms = 0.f;
             int rc = time_one(ctx, (int)k, d_samples, reps, ms);
             if (rc) return rc;
+            tune_note(ctx, "{\"step\": \"alone\", \"sub\": %zu, \"kernel\": \"%s\", \"tile\": %d, "
+                           "\"ms\": %.4f}",
+                      k, fam_name(cands[q].fam),
+                      cands[q].fam == FAM_REG ? 32 * cands[q].wt : (cands[q].fam == FAM_W2 ? 64 : 128), ms);
             if (q == 0 || ms < best) {
                 best = ms;
                 pick = cands[q];
@@ -146,6 +168,9 @@ int xeng_autotune(xeng_ctx *ctx, const void *const *d_samples, int reps)
             float ms = 0.f;
             rc = time_runs(ctx, reps, [&]() { return launch_all(ctx, d_samples); }, ms);
             if (rc) return rc;
+            tune_note(ctx, "{\"step\": \"schedule\", \"workgroups_per_cu\": %d, \"order\": %d, "
+                           "\"ms\": %.4f}",
+                      opts[q][0], opts[q][1], ms);
             if (q == 0 || ms < best) {
                 best = ms;
                 bw = opts[q][0];
@@ -167,7 +192,7 @@ int xeng_autotune(xeng_ctx *ctx, const void *const *d_samples, int reps)
     for (const Sub &s : ctx->subs) can_move |= wave_path(s.cfg) && !s.wave;
     if (ctx->subs.size() > 1 && can_move) {
         for (Sub &s : ctx->subs)
-            if (wave_path(s.cfg)) set_choice(s, FAM_W1, s.wt);
+            if (wave_path(s.cfg)) set_choice(s, FAM_WG, s.wt);
         float best_all = 0.f;
         int bw_all = 2, bo_all = 0;
         rc = tune_schedule(best_all, bw_all, bo_all);
