@@ -134,6 +134,31 @@ int xeng_samples_since_dump(const xeng_ctx *ctx, int sub, int64_t *out);
 int xeng_max_dump_samples(const xeng_ctx *ctx, int sub, int64_t *out);
 
 /*
+ * Kernel families, for xeng_set_kernel (the plan JSON names them too):
+ *   XENG_KERNEL_REGISTER   register-staging tiles of 32 x tile (any shape)
+ *   XENG_KERNEL_PERSISTENT persistent 4-wave workgroups over 128 x 128 tiles
+ *                          (N % 16 == 0 for 4-bit, N % 8 == 0 for 8-bit; the
+ *                          only one for the FP8 engine; the default)
+ *   XENG_KERNEL_ONE_WAVE   wave-private items of 128 x 64, one wave per SIMD
+ *   XENG_KERNEL_TWO_WAVE   wave-private items of 64 x 64, two waves per SIMD
+ *                          (both: 4-bit input, int8 engine, N % 16 == 0)
+ */
+#define XENG_KERNEL_REGISTER 0
+#define XENG_KERNEL_PERSISTENT 1
+#define XENG_KERNEL_ONE_WAVE 2
+#define XENG_KERNEL_TWO_WAVE 3
+
+/*
+ * Run subarray sub on kernel family `kernel` (tile: 32, 64 or 128 inputs for
+ * XENG_KERNEL_REGISTER, ignored otherwise) from the next call on. The choice
+ * falls back to the next family down that supports the subarray's shape and
+ * engine (as the plan JSON then shows). Discards anything accumulated (all
+ * subarrays restart from zero); synchronises the context stream. Errors:
+ * XENG_EINVAL, XENG_ENOMEM, XENG_EHIP.
+ */
+int xeng_set_kernel(xeng_ctx *ctx, int sub, int kernel, int tile);
+
+/*
  * Describe the launch plan (tile sizes, launch counts per call) as a
  * NUL-terminated JSON object in buf (at most len bytes). XENG_EINVAL if buf
  * is too small.

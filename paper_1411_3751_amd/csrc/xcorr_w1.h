@@ -47,7 +47,10 @@
 // Flush: each item adds its sums to `src` (the accumulator, when it holds an
 // earlier part of the integration) and writes `dst` (the accumulator, or the
 // caller's output for a correlate-and-dump), in the output layout
-// [F][N(N+1)/2][2].
+// [F][N(N+1)/2][2]. These kernels always write exact sums (a zero diagonal
+// in the raw form of the other kernels, see xcorr_wg.h); src's diagonal word
+// of row i is subtracted, so they may also finish an integration begun by
+// the other kernels.
 #pragma once
 
 #include <type_traits>
@@ -417,9 +420,6 @@ void xcorr_w1_kernel(W1Args a)
 
         // ---- flush. S: lanes l and l + 32 hold halves of the real-part sum
         // of row l % 32 of read block k.
-#pragma unroll
-        for (int k = 0; k < Ro::NRD; ++k)
-            if (Ro::as_i(k)) S[k] += __shfl_xor(S[k], 32);
         const int N = sb.n_inputs;
         const int r0 = Geo::TILE * bi;
         const int c0 = (V == 1 && R == 0) ? 128 * bj + 64 * h : (R == 0 ? Geo::TILE * bj : Geo::TILE * bi);
@@ -436,6 +436,22 @@ void xcorr_w1_kernel(W1Args a)
             (void *)((const uint2 *)(add ? sb.src : sb.dst) + cell0), (short)0, add ? nbytes : 0,
             0x00020000);
         const int lh = lane >> 5, lc = lane & 31;
+        // S[k] of row l % 32 of read block k (used as I): this wave's sums
+        // minus src's diagonal word of that row (src's -S_i in the raw form)
+#pragma unroll
+        for (int k = 0; k < Ro::NRD; ++k)
+            if (Ro::as_i(k)) {
+                S[k] += __shfl_xor(S[k], 32);
+                int kb = 0; // output block row of read block k
+#pragma unroll
+                for (int b = 0; b < Ro::NB; ++b)
+                    if (Ro::xr(b) == k) kb = Ro::ox(b);
+                const int i = r0 + 32 * kb + lc;
+                const uint32_t doff = (i < N) ? (uint32_t)((int64_t)i * (i + 1) / 2 + i - rb0) * 8u : OOR;
+                const u32x2 dg = add ? __builtin_amdgcn_raw_buffer_load_b64(srs, (int)doff, 0, 0)
+                                     : u32x2{0u, 0u};
+                S[k] -= (int32_t)dg.y;
+            }
 #pragma unroll
         for (int b = 0; b < Ro::NB; ++b) {
             // the block's sums stay in accumulation registers until here, so
@@ -489,19 +505,6 @@ void xcorr_w1_kernel(W1Args a)
     }
     // the copies issued past the end still land in this workgroup's LDS
     dma_wait<0>();
-}
-
-// Plain copy of 8-byte cells (a dump of an accumulator that already holds
-// the output convention). Grid-stride, 16 bytes per thread per step.
-__global__ __launch_bounds__(256) void copy_cells_kernel(const uint4 *__restrict__ src,
-                                                         uint4 *__restrict__ dst, size_t n16,
-                                                         const uint2 *__restrict__ src_tail,
-                                                         uint2 *__restrict__ dst_tail, int tail)
-{
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += stride)
-        dst[k] = src[k];
-    if (blockIdx.x == 0 && threadIdx.x < tail) dst_tail[threadIdx.x] = src_tail[threadIdx.x];
 }
 
 } // namespace xeng

@@ -30,12 +30,16 @@
 // Operands: re, im and ~im (= -im - 1, so that -(-8) or -(-128) never has to
 // fit in int8); 4-bit values are scaled by 16 by the nibble masks (see
 // xcorr_i8.h). The int8 engines' imaginary sums are then Im V_ij - S_i with
-// S_i = sum_t re_i; each wave also sums S_i for its rows (v_dot8_i32_i4 on
-// the raw 4-bit words with weight 1 on the real nibbles, v_dot4_i32_i8 on the
-// 8-bit real parts) and the flush adds it back, so every flush writes the
-// exact V_ij. A flush adds its sums to `src` (the accumulator, when it holds
-// an earlier part of the integration) and writes `dst` (the accumulator, or
-// the caller's output for a correlate-and-dump).
+// S_i = sum_t re_i. The accumulator keeps that raw form (the diagonal cell of
+// row i then holds -S_i, since Im V_ii = 0, and the dump subtracts it); a
+// sum that is exact already is a raw one with a zero diagonal, so both kinds
+// of launch may add into one accumulator. A flush adds its sums to `src`
+// (the accumulator, when it holds an earlier part of the integration) and
+// writes `dst`. With FUSE (the last launch of a correlate-and-dump, dst the
+// caller's output) each wave also sums S_i for its rows (v_dot8_i32_i4 on the
+// raw 4-bit words with weight 1 on the real nibbles, v_dot4_i32_i8 on the
+// 8-bit real parts) and the flush writes the exact V_ij: its own sums plus
+// S_i, plus src minus src's diagonal word of row i.
 #pragma once
 
 #include <type_traits>
@@ -144,6 +148,7 @@ __device__ __forceinline__ u32x4 wg_raw(const WgRaw &R, int k, int sd, int blk)
 
 // ... and S[x] += the real parts of its I-side words (row sums for the Im
 // correction): 4 v_dot8_i32_i4 with weights 1 on the real nibbles
+template <bool SUMS>
 __device__ __forceinline__ void wg_unpack(const WgRaw &R, int k, WgOps &o, int32_t (&S)[2])
 {
 #pragma unroll
@@ -151,8 +156,10 @@ __device__ __forceinline__ void wg_unpack(const WgRaw &R, int k, WgOps &o, int32
         const u32x4 p = wg_raw(R, k, 0, x);
         o.reI[x] = (i32x4)(p & 0xF0F0F0F0u);
         o.imI[x] = (i32x4)((p << 4) & 0xF0F0F0F0u);
+        if (SUMS) {
 #pragma unroll
-        for (int d = 0; d < 4; ++d) S[x] = __builtin_amdgcn_sdot8((int)p[d], 0x10101010, S[x], false);
+            for (int d = 0; d < 4; ++d) S[x] = __builtin_amdgcn_sdot8((int)p[d], 0x10101010, S[x], false);
+        }
     }
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
@@ -181,13 +188,17 @@ __device__ __forceinline__ void wg8_split(const WgRaw &R, int sd, int blk, i32x4
     }
 }
 
+template <bool SUMS>
 __device__ __forceinline__ void wg8_unpack(const WgRaw &R, WgOps &o, int32_t (&S)[2])
 {
 #pragma unroll
     for (int x = 0; x < 2; ++x) {
         wg8_split(R, 0, x, o.reI[x], o.imI[x]);
+        if (SUMS) {
 #pragma unroll
-        for (int d = 0; d < 4; ++d) S[x] = __builtin_amdgcn_sdot4(o.reI[x][d], 0x01010101, S[x], false);
+            for (int d = 0; d < 4; ++d)
+                S[x] = __builtin_amdgcn_sdot4(o.reI[x][d], 0x01010101, S[x], false);
+        }
     }
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
@@ -345,7 +356,7 @@ __device__ __forceinline__ uint32_t acc_word(float v) { return (uint32_t)(int32_
 
 // Two workgroups per CU (launch bounds 256 threads x 2): each one's barrier
 // and LDS latency is covered by the other's MFMAs.
-template <int ENG, int IN_BITS>
+template <int ENG, int IN_BITS, bool FUSE>
 __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
 {
     static_assert(ENG == ENG_I8 || IN_BITS == 4, "the FP8 engine takes 4-bit input");
@@ -565,7 +576,7 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
                 accR[x][y] = AccT{};
                 accI[x][y] = AccT{};
             }
-        int32_t S[2] = {0, 0}; // this lane's part of S_i of rows l % 32 of I blocks 0, 1
+        int32_t S[2] = {0, 0}; // this lane's part of S_i of rows l % 32 of I blocks 0, 1 (FUSE)
         // the stage's fragments were read by the previous step (RA); unpack
         // and multiply, then publish and read the next stage
         // The stage's fragments were read by the previous step (RA). Once
@@ -588,11 +599,11 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
             } else {
                 if (write) {
                     if constexpr (IN_BITS == 4) {
-                        wg_unpack(RA, 0, O0, S);
+                        wg_unpack<FUSE>(RA, 0, O0, S);
                         wg_mfma(O0, accR, accI);
-                        wg_unpack(RA, 1, O0, S);
+                        wg_unpack<FUSE>(RA, 1, O0, S);
                     } else {
-                        wg8_unpack(RA, O0, S);
+                        wg8_unpack<FUSE>(RA, O0, S);
                     }
                     wg_mfma_blocks<0, wg_split<IN_BITS>()>(O0, accR, accI);
                 }
@@ -618,10 +629,6 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
         int fl = lane;
         asm volatile("" : "+v"(fl));
         const int lh = fl >> 5, lc = fl & 31;
-        if constexpr (ENG == ENG_I8) {
-#pragma unroll
-            for (int x = 0; x < 2; ++x) S[x] += __shfl_xor(S[x], 32);
-        }
         const int64_t tri = (int64_t)N * (N + 1) / 2;
         const int r1 = r0 + 64 < N ? r0 + 64 : (r0 < N ? N : r0);
         const int64_t rb0 = (int64_t)r0 * (r0 + 1) / 2;
@@ -634,6 +641,19 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
         const __amdgpu_buffer_rsrc_t srs = __builtin_amdgcn_make_buffer_rsrc(
             (void *)((const uint2 *)(add ? sb.src : sb.dst) + cell0), (short)0, add ? nbytes : 0,
             0x00020000);
+        if constexpr (FUSE) {
+            // S[x] of row l % 32 of I block x: this wave's sums (int8 engines)
+            // minus src's diagonal word of that row (src's own -S_i, or 0)
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                if (ENG == ENG_I8) S[x] += __shfl_xor(S[x], 32);
+                const int i = r0 + 32 * x + lc;
+                const uint32_t doff = (i < N) ? (uint32_t)((int64_t)i * (i + 1) / 2 + i - rb0) * 8u : OOR;
+                const u32x2 dg = add ? __builtin_amdgcn_raw_buffer_load_b64(srs, (int)doff, 0, 0)
+                                     : u32x2{0u, 0u};
+                S[x] -= (int32_t)dg.y;
+            }
+        }
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -648,7 +668,7 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
                     const int rr = 8 * q + 4 * lh + e;
                     const int i = r0 + 32 * x + rr;
                     const int rel = (int)((int64_t)i * (i + 1) / 2 - rb0);
-                    sv[e] = ENG == ENG_I8 ? __shfl(S[x], rr) : 0;
+                    sv[e] = FUSE ? __shfl(S[x], rr) : 0;
 #pragma unroll
                     for (int y = 0; y < 2; ++y) {
                         const int j = c0 + 32 * y + lc;

@@ -2,7 +2,9 @@
 //
 // Owns the per-subarray int32 accumulators (packed lower triangle; the
 // imaginary words hold Im V_ij - S_i, see xcorr_wg.h, and the dump kernel
-// turns them into Im V_ij), checks the exactness bounds before any launch,
+// turns them into Im V_ij; a correlate-and-dump writes exact sums straight to
+// the caller's output from its last launch), checks the exactness bounds
+// before any launch,
 // splits each call into segments of at most SEG_T samples, and launches:
 //   - 4-bit subarrays with N a multiple of 16 on the int8 engine: the
 //     one-wave-per-SIMD kernel (xcorr_w1.h), all such subarrays in one launch
@@ -72,8 +74,7 @@ struct Sub {
     int64_t since_dump = 0;    // samples accumulated since the last reset
     int64_t max_dump = 0;      // exactness bound on since_dump
     bool acc_zero = true;      // accumulator logically zero (next launch overwrites)
-    bool wave = false;         // handled by a persistent kernel (one launch per group); its
-                               // accumulator holds the output convention
+    bool wave = false;         // handled by a persistent kernel (one launch per group)
     bool w1 = false;           // ... a wave-private one
     int wv = 0;                // which one: 1 (one wave per SIMD) or 2 (two)
     int wt = 4;                // register kernel: wave tile edge in 16-row sub-blocks
@@ -425,15 +426,20 @@ int launch_wave(xeng_ctx *ctx, WavePlan &p, const void *const *d_samples, void *
         }
         a.items = p.d_items;
         a.wg_begin = p.d_wg_begin;
-        if (p.engine == XENG_ENGINE_FP8)
-            hipLaunchKernelGGL((xeng::xcorr_wg_kernel<xeng::ENG_F8, 4>), dim3(p.n_wg),
-                               dim3(xeng::WG_THREADS), 0, ctx->stream, a);
-        else if (p.in_bits == 4)
-            hipLaunchKernelGGL((xeng::xcorr_wg_kernel<xeng::ENG_I8, 4>), dim3(p.n_wg),
-                               dim3(xeng::WG_THREADS), 0, ctx->stream, a);
-        else
-            hipLaunchKernelGGL((xeng::xcorr_wg_kernel<xeng::ENG_I8, 8>), dim3(p.n_wg),
-                               dim3(xeng::WG_THREADS), 0, ctx->stream, a);
+        // the launch that writes the caller's output sums S_i and writes exact
+        // sums; the others leave the raw form in the accumulator
+        const bool fuse = last && out;
+        const dim3 g(p.n_wg), b(xeng::WG_THREADS);
+        if (p.engine == XENG_ENGINE_FP8) {
+            if (fuse) hipLaunchKernelGGL((xeng::xcorr_wg_kernel<xeng::ENG_F8, 4, true>), g, b, 0, ctx->stream, a);
+            else hipLaunchKernelGGL((xeng::xcorr_wg_kernel<xeng::ENG_F8, 4, false>), g, b, 0, ctx->stream, a);
+        } else if (p.in_bits == 4) {
+            if (fuse) hipLaunchKernelGGL((xeng::xcorr_wg_kernel<xeng::ENG_I8, 4, true>), g, b, 0, ctx->stream, a);
+            else hipLaunchKernelGGL((xeng::xcorr_wg_kernel<xeng::ENG_I8, 4, false>), g, b, 0, ctx->stream, a);
+        } else {
+            if (fuse) hipLaunchKernelGGL((xeng::xcorr_wg_kernel<xeng::ENG_I8, 8, true>), g, b, 0, ctx->stream, a);
+            else hipLaunchKernelGGL((xeng::xcorr_wg_kernel<xeng::ENG_I8, 8, false>), g, b, 0, ctx->stream, a);
+        }
         HIP_TRY(hipGetLastError());
         if (!(last && out))
             for (int k : p.subs) ctx->subs[k].acc_zero = false;
@@ -441,21 +447,10 @@ int launch_wave(xeng_ctx *ctx, WavePlan &p, const void *const *d_samples, void *
     return XENG_OK;
 }
 
+// Every accumulator is in the raw form (exact sums are raw sums with a zero
+// diagonal), so one dump kernel serves all kernel families.
 int dump_device(const Sub &s, uint32_t *out, hipStream_t st)
 {
-    if (s.wave) {
-        // the accumulator already holds the output convention
-        const size_t cells = (size_t)s.tri * (size_t)s.cfg.n_chans;
-        const size_t n16 = cells / 2;
-        const int tail = (int)(cells % 2);
-        int blocks = (int)std::min<size_t>((n16 + 255) / 256, 8192);
-        if (blocks < 1) blocks = 1;
-        hipLaunchKernelGGL(xeng::copy_cells_kernel, dim3(blocks), dim3(256), 0, st,
-                           (const uint4 *)s.d_acc, (uint4 *)out, n16,
-                           (const uint2 *)s.d_acc + 2 * n16, (uint2 *)out + 2 * n16, tail);
-        HIP_TRY(hipGetLastError());
-        return XENG_OK;
-    }
     const unsigned gx = (unsigned)((s.tri + xeng::DUMP_PER_WG - 1) / xeng::DUMP_PER_WG);
     for (int c0 = 0; c0 < s.cfg.n_chans; c0 += 65535) {
         const int nc = std::min(65535, s.cfg.n_chans - c0);
@@ -866,6 +861,30 @@ int xeng_correlate_dump(xeng_ctx *ctx, const void *const *d_samples, void *const
         s.acc_zero = true;
         s.since_dump = 0;
     }
+    return XENG_OK;
+}
+
+int xeng_set_kernel(xeng_ctx *ctx, int sub, int kernel, int tile)
+{
+    if (!ctx) return fail(XENG_EINVAL, "ctx is NULL");
+    if (sub < 0 || sub >= (int)ctx->subs.size()) return fail(XENG_EINVAL, "sub %d out of range", sub);
+    if (kernel < XENG_KERNEL_REGISTER || kernel > XENG_KERNEL_TWO_WAVE)
+        return fail(XENG_EINVAL, "unknown kernel family %d", kernel);
+    if (kernel == XENG_KERNEL_REGISTER && tile != 32 && tile != 64 && tile != 128)
+        return fail(XENG_EINVAL, "register-staging tile %d is not 32, 64 or 128", tile);
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    const int fam = kernel == XENG_KERNEL_REGISTER ? FAM_REG
+                    : kernel == XENG_KERNEL_PERSISTENT ? FAM_WG
+                    : kernel == XENG_KERNEL_ONE_WAVE ? FAM_W1 : FAM_W2;
+    Sub &s = ctx->subs[sub];
+    set_choice(s, fam, kernel == XENG_KERNEL_REGISTER ? tile / 32 : s.wt);
+    int rc = replan(ctx);
+    if (rc) return rc;
+    for (Sub &t : ctx->subs) {
+        t.acc_zero = true;
+        t.since_dump = 0;
+    }
+    ctx->tuned = false;
     return XENG_OK;
 }
 

@@ -14,6 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libxeng.so")
 
 XENG_OK, XENG_EINVAL, XENG_ERANGE, XENG_ENOMEM, XENG_EHIP = 0, 1, 2, 3, 4
+KERNEL_REGISTER, KERNEL_PERSISTENT, KERNEL_ONE_WAVE, KERNEL_TWO_WAVE = 0, 1, 2, 3
 ENGINE_I8, ENGINE_FP8 = 0, 1
 MAX_DUMP_SAMPLES_4BIT = 16777215
 MAX_DUMP_SAMPLES_8BIT = 65535
@@ -22,7 +23,7 @@ MAX_CALL_SAMPLES_FP8 = 32768
 EXPORTS = (
     "xeng_create", "xeng_correlate", "xeng_dump", "xeng_correlate_dump", "xeng_destroy",
     "xeng_set_stream",
-    "xeng_samples_since_dump", "xeng_max_dump_samples", "xeng_plan_describe",
+    "xeng_samples_since_dump", "xeng_max_dump_samples", "xeng_plan_describe", "xeng_set_kernel",
     "xeng_strerror", "xeng_last_error",
     "xeng_stream_create", "xeng_stream_next_slot", "xeng_stream_push", "xeng_stream_dump_wait",
     "xeng_stream_gulp_times", "xeng_stream_gulps", "xeng_stream_backlog", "xeng_stream_destroy",
@@ -97,6 +98,8 @@ def load():
     lib.xeng_max_dump_samples.restype = i32
     lib.xeng_plan_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
     lib.xeng_plan_describe.restype = i32
+    lib.xeng_set_kernel.argtypes = [vp, i32, i32, i32]
+    lib.xeng_set_kernel.restype = i32
     lib.xeng_strerror.argtypes = [i32]
     lib.xeng_strerror.restype = ctypes.c_char_p
     lib.xeng_last_error.argtypes = []
@@ -234,6 +237,10 @@ class Correlator:
     def correlate(self, samples):
         """samples: one device tensor (or device pointer int) per subarray."""
         _check(self._lib.xeng_correlate(self._ctx, self._sample_ptrs(samples)))
+
+    def set_kernel(self, kernel: int, k: int = 0, tile: int = 64):
+        """Pin subarray k to a kernel family (KERNEL_*); discards accumulated sums."""
+        _check(self._lib.xeng_set_kernel(self._ctx, int(k), int(kernel), int(tile)))
 
     def autotune(self, samples, reps: int = 5):
         """Time the kernel and schedule choices on these samples and keep the fastest."""

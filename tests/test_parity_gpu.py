@@ -218,3 +218,30 @@ def test_correlate_dump_one_call(torch_cuda, oracle_lib):
         for (N, F, T, bits), x, y, o in zip(shapes, a, b_, outs):
             want = oracle_lib.narrow(oracle_lib.correlate(x, bits) + oracle_lib.correlate(y, bits))
             assert np.array_equal(o, want), (N, T, bits)
+
+
+@pytest.mark.parametrize("kernel", [0, 1, 2, 3])
+@pytest.mark.parametrize("N,F,T", [(48, 3, 100), (144, 2, 333), (256, 2, 70000), (512, 1, 257)])
+def test_every_kernel_family(torch_cuda, oracle_lib, kernel, N, F, T):
+    # each kernel family pinned with xeng_set_kernel: two calls then a dump,
+    # then a correlate-and-dump after one call (its flush adds the
+    # accumulator's raw sums and writes exact ones), all exact
+    from paper_1411_3751_amd import Correlator
+    torch = torch_cuda
+    print("case kernel=%d N=%d F=%d T=%d" % (kernel, N, F, T), flush=True)
+    rng = np.random.default_rng(kernel * 1000 + N + T)
+    a = rand_stream(rng, T, F, N, 4)
+    b = rand_stream(rng, T, F, N, 4)
+    da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    wa, wb = oracle_lib.correlate(a, 4), oracle_lib.correlate(b, 4)
+    with Correlator([dict(n_inputs=N, n_chans=F, n_time=T)]) as c:
+        c.set_kernel(kernel, tile=64)
+        print("plan", c.plan()["subarrays"][0]["kernel"], flush=True)
+        c.correlate([da])
+        c.correlate([db])
+        assert np.array_equal(c.dump()[0].cpu().numpy(), oracle_lib.narrow(wa + wb))
+        c.correlate([db])
+        got = c.correlate_dump([da])[0].cpu().numpy()
+        assert np.array_equal(got, oracle_lib.narrow(wa + wb))
+        got = c.correlate_dump([db])[0].cpu().numpy()
+        assert np.array_equal(got, oracle_lib.narrow(wb))
