@@ -801,19 +801,19 @@ def xengine_bench(args):
     torch.cuda.synchronize()
 
     # timed region: K whole steps between two events, nothing else enqueued
-    clock = ClockSampler()
     n = args.steps
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    clock.start()
     t_start.record(stream)
     for _ in range(n):
         step()
     t_end.record(stream)
     torch.cuda.synchronize()
-    clock.stop()
     ms_step = t_start.elapsed_time(t_end) / n
+    # clock under the same load, read between batches of queued steps (not
+    # during the timed region: the readings take host time)
+    mhz = clock_under_load(step, max(8, int(12.0 / max(ms_step, 1e-3))))
 
     # kernel pass (after the timed region): an event pair on the stream
     # around each correlate call times that launch of the tile kernel (with
@@ -873,12 +873,12 @@ def xengine_bench(args):
         "ms_kernel": round(ms_kernel, 4),
         "ms_kernel_p50": round(sorted(k_ms)[n // 2], 4),
     }
-    mhz = clock.mhz()
     if mhz:
-        res["gfxclk_mhz_timed"] = round(mhz, 0)
+        res["gfxclk_mhz"] = round(mhz, 0)
         res["pct_int8_peak_at_measured_clock"] = round(
             100.0 * value / (PEAK_INT8_OPS * mhz / 2400.0 / 1e12), 2)
-        res["clock_source"] = clock.source
+        res["clock_source"] = ("amdsmi gpu_metrics current_gfxclks, mean over XCDs, median of "
+                               "readings between batches of the same steps after the timed region")
     if small:
         res["roofline"] = {"bound": "hbm", "achieved": round(hbm_bytes / (ms_kernel * 1e-3) / 1e9, 1),
                            "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -913,68 +913,37 @@ def settle(step, seconds):
     return n
 
 
-class ClockSampler:
-    """Samples the GPU's graphics clock (amdsmi GPU metrics) in a background
-    thread while a region runs; mhz() is the mean of the samples, or None
-    where the metrics are not readable."""
+def clock_under_load(step, per_batch, batches=12):
+    """Median graphics clock (MHz, mean over the XCDs) read from amdsmi GPU
+    metrics between batches of `per_batch` queued steps, or None where the
+    metrics are not readable. Each reading is taken while the previous batch
+    still runs on the device."""
+    import statistics
 
-    def __init__(self, period_s=0.002):
-        self.period = period_s
-        self.samples = []
-        self.source = None
-        self._h = None
-        self._stop = False
-        self._t = None
-        try:
-            import amdsmi
-            amdsmi.amdsmi_init()
-            self._smi = amdsmi
-            self._h = amdsmi.amdsmi_get_processor_handles()[0]
-        except Exception as e:  # no amdsmi, no device, no permission
-            log("clock sampling unavailable: %s" % e)
-            self._h = None
-
-    def _read(self):
-        m = self._smi.amdsmi_get_gpu_metrics_info(self._h)
-        for key in ("current_gfxclk", "average_gfxclk_frequency"):
-            v = m.get(key)
-            if isinstance(v, (int, float)) and 0 < v < 10000:
-                self.source = "amdsmi gpu_metrics " + key
-                return float(v)
-        v = m.get("current_gfxclks")
-        if isinstance(v, (list, tuple)):
-            vals = [float(x) for x in v if isinstance(x, (int, float)) and 0 < x < 10000]
-            if vals:
-                self.source = "amdsmi gpu_metrics current_gfxclks (mean over XCDs)"
-                return sum(vals) / len(vals)
+    import torch
+    try:
+        import amdsmi
+        amdsmi.amdsmi_init()
+        h = amdsmi.amdsmi_get_processor_handles()[0]
+    except Exception as e:  # no amdsmi, no device, no permission
+        log("clock readings unavailable: %s" % e)
         return None
-
-    def _run(self):
-        while not self._stop:
-            try:
-                v = self._read()
-            except Exception:
-                v = None
-            if v:
-                self.samples.append(v)
-            time.sleep(self.period)
-
-    def start(self):
-        if self._h is None:
-            return
-        import threading
-        self._stop = False
-        self._t = threading.Thread(target=self._run, daemon=True)
-        self._t.start()
-
-    def stop(self):
-        if self._t is not None:
-            self._stop = True
-            self._t.join()
-            self._t = None
-
-    def mhz(self):
-        return sum(self.samples) / len(self.samples) if self.samples else None
+    vals = []
+    for b in range(batches):
+        for _ in range(per_batch):
+            step()
+        if b < 2:
+            continue  # the metrics table lags the load
+        try:
+            m = amdsmi.amdsmi_get_gpu_metrics_info(h)
+            xs = [float(x) for x in m.get("current_gfxclks", []) if isinstance(x, (int, float))
+                  and 0 < x < 10000]
+            if xs:
+                vals.append(sum(xs) / len(xs))
+        except Exception:
+            pass
+    torch.cuda.synchronize()
+    return statistics.median(vals) if vals else None
 
 
 def stream_figures(args):
