@@ -124,6 +124,27 @@ int xeng_correlate_dump(xeng_ctx *ctx, const void *const *d_samples, void *const
 /* Release the context and its device memory (waits for its stream). NULL is a no-op. */
 int xeng_destroy(xeng_ctx *ctx);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one
+ * subarray's correlate-and-dump without a context. Writes the exact sums of
+ * the n_time samples at d_samples (device, layout and formats as for
+ * xeng_correlate) to d_out (device int32 [n_chans][N(N+1)/2][2], 8-byte
+ * aligned), enqueued on hip_stream (a hipStream_t; NULL = null stream), and
+ * returns. It calls no hipMalloc or hipFree: the tile schedule is rebuilt on
+ * the device on every call in a library-owned static device array of
+ * 4,210,692 bytes, which each GPU the library runs on holds until the process
+ * ends. Calls that overlap on one GPU (on different streams, or from several
+ * threads) race on that array; order them. Limits (XENG_EINVAL, nothing
+ * launched): the persistent kernel's shapes (N a multiple of 16 for 4-bit
+ * input and the FP8 engine, of 8 for 8-bit input), n_time <= 32768 samples
+ * (one launch), and n_chans * nb (nb + 1) / 2 <= 524288 tiles with
+ * nb = ceil(N / 128). Other errors: XENG_EINVAL (NULL or misaligned
+ * pointers, bad shape), XENG_EHIP.
+ */
+int xeng_correlate_dump_static(const xeng_subarray *sub, const void *d_samples, void *d_out,
+                               void *hip_stream);
+
 /* Point the context at another HIP stream (NULL = null stream) for later calls. */
 int xeng_set_stream(xeng_ctx *ctx, void *hip_stream);
 

@@ -961,3 +961,4 @@ int xeng_plan_describe(const xeng_ctx *ctx, char *buf, size_t len)
 #include "xeng_tune.h"
 #include "xeng_ingest.h"
 #include "xeng_fengine.h"
+#include "xeng_static.h"

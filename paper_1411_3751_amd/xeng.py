@@ -22,6 +22,7 @@ MAX_CALL_SAMPLES_FP8 = 32768
 
 EXPORTS = (
     "xeng_create", "xeng_correlate", "xeng_dump", "xeng_correlate_dump", "xeng_destroy",
+    "xeng_correlate_dump_static",
     "xeng_set_stream",
     "xeng_samples_since_dump", "xeng_max_dump_samples", "xeng_plan_describe", "xeng_set_kernel",
     "xeng_strerror", "xeng_last_error",
@@ -88,6 +89,8 @@ def load():
     lib.xeng_dump.restype = i32
     lib.xeng_correlate_dump.argtypes = [vp, pp, pp, i32, i32]
     lib.xeng_correlate_dump.restype = i32
+    lib.xeng_correlate_dump_static.argtypes = [ctypes.POINTER(Subarray), vp, vp, vp]
+    lib.xeng_correlate_dump_static.restype = i32
     lib.xeng_destroy.argtypes = [vp]
     lib.xeng_destroy.restype = i32
     lib.xeng_set_stream.argtypes = [vp, vp]
@@ -182,6 +185,20 @@ def _ptrs(values):
     for k, v in enumerate(values):
         arr[k] = v
     return arr
+
+
+def correlate_dump_static(subarray, samples, out, stream=None):
+    """xeng_correlate_dump_static: one subarray's exact sums into out (a
+    device int32 tensor [F][tri(N)][2]) without a context and without device
+    allocation; enqueued on stream (a torch stream or hipStream_t handle)."""
+    lib = load()
+    s = subarray if isinstance(subarray, Subarray) else Subarray(
+        int(subarray["n_inputs"]), int(subarray["n_chans"]), int(subarray["n_time"]),
+        int(subarray.get("in_bits", 4)), int(subarray.get("engine", ENGINE_I8)))
+    p = samples if isinstance(samples, int) else samples.data_ptr()
+    o = out if isinstance(out, int) else out.data_ptr()
+    _check(lib.xeng_correlate_dump_static(ctypes.byref(s), ctypes.c_void_p(p), ctypes.c_void_p(o),
+                                          ctypes.c_void_p(_stream_handle(stream))))
 
 
 class Correlator:
