@@ -28,12 +28,12 @@ PEAK_HBM_GBS = 8000.0            # MI355X HBM3E, GB/s
 CHANNEL_HZ = 24.0e3              # channel width of the paper's F-engine (Section 2)
 
 
-KERNEL = "xcorr_w1_kernel"        # the dominant kernel of a step
+KERNEL = "xcorr_wg_kernel"        # the dominant kernel of a step
 PROFILES = os.path.join(ROOT, "profiles")
 # device code the traffic counters depend on (the kernel and the helpers it
 # uses); host-only changes elsewhere do not invalidate them
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1411_3751_amd", "csrc", f)
-                  for f in ("xcorr_w1.h", "xcorr_wg.h", "xcorr_i8.h")]
+                  for f in ("xcorr_wg.h", "xcorr_i8.h")]
 
 
 def kernel_source_hash(files=None) -> str:
@@ -101,7 +101,22 @@ def cpu_baseline(samples, n_inputs, n_chans, n_time, in_bits=4, budget_s=15.0):
             "kind": "oracle",
             "sample": "%d of %d channels of the same gulp (N=%d, T=%d), %.1f s" % (
                 n_sel, n_chans, n_inputs, n_time, dt),
-            "cmac_per_s": cmac / dt}
+            "cmac_per_s": cmac / dt,
+            # the oracle runs one channel per thread: the calibration call
+            # above (one channel) ran on one core
+            "cmac_per_s_one_core": tri * n_time / one,
+            "cpu_model": cpu_model()}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 STREAM_CFG = dict(n_inputs=512, n_chans=2400, n_time=8192, in_bits=4)  # 2400 x 24 kHz, 0.341 s gulps

@@ -61,6 +61,7 @@ extern "C" {
 #define XENG_ERANGE 2 /* the call would break the exactness bound; nothing launched */
 #define XENG_ENOMEM 3 /* device allocation failed */
 #define XENG_EHIP 4   /* a HIP runtime call failed; see xeng_last_error() */
+#define XENG_EBUSY 5  /* non-blocking stream: no free ring slot, the gulp was counted as dropped */
 
 #define XENG_ENGINE_I8 0  /* int8 MFMA, int32 accumulation */
 #define XENG_ENGINE_FP8 1 /* FP8 (OCP e4m3) MFMA, fp32 partial sums; in_bits == 4 and N % 16 == 0 */
@@ -145,7 +146,8 @@ int xeng_destroy(xeng_ctx *ctx);
 int xeng_correlate_dump_static(const xeng_subarray *sub, const void *d_samples, void *d_out,
                                void *hip_stream);
 
-/* Point the context at another HIP stream (NULL = null stream) for later calls. */
+/* Point the context at another HIP stream (NULL = null stream) for later calls;
+ * work already enqueued on the old stream is ordered before them. */
 int xeng_set_stream(xeng_ctx *ctx, void *hip_stream);
 
 /* Samples accumulated into subarray sub since its last reset. */
@@ -283,7 +285,10 @@ int xeng_stream_create(const xeng_subarray *sub, int n_slots, int dump_every,
  * returns the slot's device pointer and the ingest stream (a hipStream_t).
  * The caller enqueues the work that fills the slot (a copy, a producer
  * kernel) on that stream and then calls xeng_stream_push. Calling it twice
- * without a push returns the same slot.
+ * without a push returns the same slot. In non-blocking mode, if that slot's
+ * previous gulp has not been correlated yet (the engine is behind), the gulp
+ * is dropped instead (as by xeng_stream_drop): *d_slot = NULL and
+ * XENG_EBUSY; the caller discards the gulp's data.
  */
 int xeng_stream_next_slot(xeng_stream *s, void **d_slot, void **ingest_stream);
 
@@ -311,8 +316,51 @@ int xeng_stream_dump_wait(xeng_stream *s, int64_t d, void **d_dump);
  */
 int xeng_stream_gulp_times(xeng_stream *s, int64_t g, float *arrive_ms, float *ready_ms);
 
-/* Number of gulps pushed so far. */
+/* Number of gulps so far, pushed or dropped. */
 int xeng_stream_gulps(const xeng_stream *s, int64_t *out);
+
+/*
+ * Overload handling (Section 2.4: lost data is counted, not corrected). The
+ * next gulp is lost (for instance, too few of its packets arrived): it is
+ * counted, adds nothing to any sum, and still counts towards the dump and
+ * fast-autocorrelation cadences, so every dump covers the same span of
+ * time. *gulp (may be NULL) receives its index. A slot obtained by
+ * xeng_stream_next_slot and not pushed is given back.
+ */
+int xeng_stream_drop(xeng_stream *s, int64_t *gulp);
+
+/* on != 0: xeng_stream_next_slot drops a gulp whose slot is still busy
+ * instead of making the ingest stream wait for it (XENG_EBUSY). */
+int xeng_stream_set_nonblocking(xeng_stream *s, int on);
+
+typedef struct {
+    int64_t gulps;      /* pushed + dropped */
+    int64_t correlated; /* pushed */
+    int64_t dropped;    /* dropped (xeng_stream_drop, or no free slot in non-blocking mode) */
+    int64_t dumps;      /* dumps enqueued */
+    int64_t fast_dumps; /* fast-cadence autocorrelation dumps enqueued */
+    int64_t backlog;    /* gulps whose device work has not finished (as xeng_stream_backlog) */
+} xeng_stream_counts;
+
+int xeng_stream_stats(xeng_stream *s, xeng_stream_counts *out);
+
+/*
+ * Fast-cadence autocorrelations inside the stream (Section 2.6: total power
+ * of chosen inputs dumped more often than the cross power). Before the first
+ * gulp: select n inputs of the subarray (host array, indices in [0, N)) and
+ * dump their autocorrelations every `every` gulps (pushed or dropped) into a
+ * device buffer int32 [n_chans][n] (Re V_ii in selection order), copied to
+ * host_out[k % n_host] if host buffers (n_chans * n * 4 bytes, preferably
+ * pinned) are given; the selected cells are then cleared. The main dump
+ * reports the selected autocorrelations since their last fast dump. Errors:
+ * XENG_EINVAL, XENG_ENOMEM, XENG_EHIP.
+ */
+int xeng_stream_set_fast_autos(xeng_stream *s, const int32_t *inputs, int n, int every,
+                               void *const *host_out, int n_host);
+
+/* Wait until fast dump k (0-based, one of the last two) is complete; *d_out
+ * (may be NULL) receives its device buffer. */
+int xeng_stream_fast_wait(xeng_stream *s, int64_t k, void **d_out);
 
 /* Gulps pushed whose correlation (and dump, if they complete one) has not yet
  * finished on the device: 0 while the engine keeps up; a count that grows

@@ -621,6 +621,7 @@ const char *xeng_strerror(int code)
     case XENG_ERANGE: return "exactness bound exceeded";
     case XENG_ENOMEM: return "out of device memory";
     case XENG_EHIP: return "HIP runtime error";
+    case XENG_EBUSY: return "no free ring slot (gulp dropped)";
     default: return "unknown error";
     }
 }
@@ -734,7 +735,18 @@ int xeng_destroy(xeng_ctx *ctx)
 int xeng_set_stream(xeng_ctx *ctx, void *hip_stream)
 {
     if (!ctx) return fail(XENG_EINVAL, "ctx is NULL");
-    ctx->stream = (hipStream_t)hip_stream;
+    hipStream_t next = (hipStream_t)hip_stream;
+    if (next != ctx->stream) {
+        // work already queued on the old stream comes first on the new one
+        hipEvent_t ev = nullptr;
+        HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        hipError_t e = hipEventRecord(ev, ctx->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(next, ev, 0);
+        (void)hipEventDestroy(ev);
+        if (e != hipSuccess)
+            return fail(XENG_EHIP, "ordering the new stream after the old: %s", hipGetErrorString(e));
+    }
+    ctx->stream = next;
     return XENG_OK;
 }
 

@@ -13,7 +13,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libxeng.so")
 
-XENG_OK, XENG_EINVAL, XENG_ERANGE, XENG_ENOMEM, XENG_EHIP = 0, 1, 2, 3, 4
+XENG_OK, XENG_EINVAL, XENG_ERANGE, XENG_ENOMEM, XENG_EHIP, XENG_EBUSY = 0, 1, 2, 3, 4, 5
 KERNEL_REGISTER, KERNEL_PERSISTENT, KERNEL_ONE_WAVE, KERNEL_TWO_WAVE = 0, 1, 2, 3
 ENGINE_I8, ENGINE_FP8 = 0, 1
 MAX_DUMP_SAMPLES_4BIT = 16777215
@@ -28,6 +28,8 @@ EXPORTS = (
     "xeng_strerror", "xeng_last_error",
     "xeng_stream_create", "xeng_stream_next_slot", "xeng_stream_push", "xeng_stream_dump_wait",
     "xeng_stream_gulp_times", "xeng_stream_gulps", "xeng_stream_backlog", "xeng_stream_destroy",
+    "xeng_stream_drop", "xeng_stream_set_nonblocking", "xeng_stream_stats",
+    "xeng_stream_set_fast_autos", "xeng_stream_fast_wait",
     "xeng_autotune", "xeng_graph_create", "xeng_graph_launch", "xeng_graph_destroy",
     "xeng_set_fast_autos", "xeng_dump_fast_autos",
     "xeng_ingest_create", "xeng_ingest_packet_stride", "xeng_ingest_gulp", "xeng_ingest_stats_get",
@@ -68,6 +70,12 @@ class Subarray(ctypes.Structure):
 
 
 _lib = None
+
+
+class StreamStats(ctypes.Structure):
+    _fields_ = [("gulps", ctypes.c_int64), ("correlated", ctypes.c_int64),
+                ("dropped", ctypes.c_int64), ("dumps", ctypes.c_int64),
+                ("fast_dumps", ctypes.c_int64), ("backlog", ctypes.c_int64)]
 
 
 def load():
@@ -123,6 +131,16 @@ def load():
     lib.xeng_stream_gulps.restype = i32
     lib.xeng_stream_backlog.argtypes = [vp, ctypes.POINTER(i64)]
     lib.xeng_stream_backlog.restype = i32
+    lib.xeng_stream_drop.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.xeng_stream_drop.restype = i32
+    lib.xeng_stream_set_nonblocking.argtypes = [vp, i32]
+    lib.xeng_stream_set_nonblocking.restype = i32
+    lib.xeng_stream_stats.argtypes = [vp, ctypes.POINTER(StreamStats)]
+    lib.xeng_stream_stats.restype = i32
+    lib.xeng_stream_set_fast_autos.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), i32, i32, pp, i32]
+    lib.xeng_stream_set_fast_autos.restype = i32
+    lib.xeng_stream_fast_wait.argtypes = [vp, i64, ctypes.POINTER(vp)]
+    lib.xeng_stream_fast_wait.restype = i32
     lib.xeng_stream_destroy.argtypes = [vp]
     lib.xeng_stream_destroy.restype = i32
     lib.xeng_ingest_create.argtypes = [ctypes.POINTER(Subarray), ctypes.POINTER(PacketFormat),
@@ -403,10 +421,43 @@ class Stream:
                                             len(self._host), ctypes.byref(self._s)))
 
     def next_slot(self):
-        """(device pointer of the next gulp's slot, ingest hipStream_t handle)."""
+        """(device pointer of the next gulp's slot, ingest hipStream_t handle);
+        (None, None) when a non-blocking stream dropped the gulp."""
         p, st = ctypes.c_void_p(), ctypes.c_void_p()
-        _check(self._lib.xeng_stream_next_slot(self._s, ctypes.byref(p), ctypes.byref(st)))
+        rc = self._lib.xeng_stream_next_slot(self._s, ctypes.byref(p), ctypes.byref(st))
+        if rc == XENG_EBUSY:
+            return None, None
+        _check(rc)
         return p.value, st.value
+
+    def drop(self) -> int:
+        """Count the next gulp as lost; returns its index."""
+        g = ctypes.c_int64()
+        _check(self._lib.xeng_stream_drop(self._s, ctypes.byref(g)))
+        return g.value
+
+    def set_nonblocking(self, on: bool = True):
+        _check(self._lib.xeng_stream_set_nonblocking(self._s, 1 if on else 0))
+
+    def stats(self) -> dict:
+        st = StreamStats()
+        _check(self._lib.xeng_stream_stats(self._s, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in StreamStats._fields_}
+
+    def set_fast_autos(self, inputs, every: int, host_out=None):
+        """Dump the autocorrelations of `inputs` every `every` gulps (host
+        int32 tensors [F][len(inputs)], preferably pinned, if given)."""
+        arr = (ctypes.c_int32 * len(inputs))(*[int(i) for i in inputs])
+        hp = _ptrs([h.data_ptr() for h in host_out]) if host_out else None
+        _check(self._lib.xeng_stream_set_fast_autos(self._s, arr, len(inputs), int(every), hp,
+                                                   len(host_out) if host_out else 0))
+        self._fast_host = list(host_out) if host_out else []
+
+    def fast_wait(self, k: int) -> int:
+        """Wait for fast dump k; returns the device pointer of its buffer."""
+        p = ctypes.c_void_p()
+        _check(self._lib.xeng_stream_fast_wait(self._s, int(k), ctypes.byref(p)))
+        return p.value
 
     def push(self) -> int:
         g = ctypes.c_int64()

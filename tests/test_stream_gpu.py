@@ -129,3 +129,97 @@ def test_stream_errors(torch_cuda):
         with pytest.raises(XengError) as ei:
             st.dump_wait(0)
         assert ei.value.code == XENG_EINVAL
+
+
+def test_stream_drops_and_fast_autos(torch_cuda, oracle_lib):
+    # gulps 5 and 7 are dropped (7 ends dump 1): every dump covers the same
+    # span of gulps and sums only the pushed ones; the autocorrelations of 4
+    # selected inputs are dumped and cleared every 2 gulps inside the stream
+    import synth.gpu
+    from paper_1411_3751_amd import Stream
+    torch = torch_cuda
+    print("case stream drops + fast autos", flush=True)
+    N, F, T, every, fast_every, n_gulps = 64, 8, 512, 4, 2, 10
+    sel = [0, 3, 17, 63]
+    drops = {5, 7}
+    seed, sigma = 77, 2.5
+    tone = drift_tone(F, T)
+    gen = synth.gpu.DeviceStream(seed, F, N, 4, sigma, tone=tone, t_total=n_gulps * T)
+    shape = (F, N * (N + 1) // 2, 2)
+    hd = [torch.empty(shape, dtype=torch.int32, pin_memory=True) for _ in range(3)]
+    fh = [torch.empty((F, len(sel)), dtype=torch.int32, pin_memory=True) for _ in range(6)]
+    with Stream(dict(n_inputs=N, n_chans=F, n_time=T), n_slots=3, dump_every=every,
+                host_dumps=hd) as st:
+        st.set_fast_autos(sel, fast_every, host_out=fh)
+        for g in range(n_gulps):
+            if g in drops:
+                assert st.drop() == g
+                continue
+            ptr, ist = st.next_slot()
+            gen.fill(ptr, g * T, T, ist)
+            st.push()
+        st.dump_wait(1)
+        st.fast_wait(4)
+        stats = st.stats()
+        dumps = [hd[d].numpy().copy() for d in range(2)]
+        fasts = [fh[k].numpy().copy() for k in range(5)]
+    assert stats["gulps"] == n_gulps and stats["dropped"] == 2 and stats["correlated"] == 8
+    assert stats["dumps"] == 2 and stats["fast_dumps"] == 5
+    per_gulp = []
+    for g in range(n_gulps):
+        x, _, _ = synth.stream(seed, T, F, N, 4, sigma, t0=g * T, tone=tone)
+        per_gulp.append(oracle_lib.correlate(x, 4) if g not in drops else None)
+    diag = [i * (i + 1) // 2 + i for i in sel]
+    for d in range(2):
+        acc = sum(per_gulp[g] for g in range(d * every, (d + 1) * every) if g not in drops)
+        want = oracle_lib.narrow(acc)
+        # every main dump here falls on a fast dump, which cleared the selected autos
+        want[:, diag, 0] = 0
+        assert np.array_equal(dumps[d], want), d
+    for k in range(5):
+        acc = sum(per_gulp[g] for g in range(k * fast_every, (k + 1) * fast_every) if g not in drops)
+        assert np.array_equal(fasts[k], acc[:, diag, 0].astype(np.int32)), k
+
+
+def test_stream_nonblocking_drops_are_counted_and_exact(torch_cuda, oracle_lib):
+    # a slow producer on the ingest stream keeps the two slots busy: in
+    # non-blocking mode next_slot drops gulps instead of waiting; whichever
+    # gulps were dropped, each dump equals the oracle over the pushed ones
+    import synth.gpu
+    from paper_1411_3751_amd import Stream
+    torch = torch_cuda
+    print("case stream non-blocking overload", flush=True)
+    N, F, T, every, n_gulps = 128, 16, 4096, 6, 24
+    seed, sigma = 78, 2.5
+    tone = drift_tone(F, T)
+    gen = synth.gpu.DeviceStream(seed, F, N, 4, sigma, tone=tone, t_total=n_gulps * T)
+    slow = synth.gpu.DeviceStream(seed + 1, 512, 4096, 4, sigma, tone=None, t_total=256)
+    ballast = torch.empty((256, 512, 4096), dtype=torch.uint8, device="cuda")
+    shape = (F, N * (N + 1) // 2, 2)
+    hd = [torch.empty(shape, dtype=torch.int32, pin_memory=True) for _ in range(4)]
+    pushed = []
+    with Stream(dict(n_inputs=N, n_chans=F, n_time=T), n_slots=2, dump_every=every,
+                host_dumps=hd) as st:
+        st.set_nonblocking(True)
+        for g in range(n_gulps):
+            ptr, ist = st.next_slot()
+            if ptr is None:
+                continue
+            slow.fill(ballast.data_ptr(), 0, 256, ist)  # a producer that takes a while
+            gen.fill(ptr, g * T, T, ist)
+            st.push()
+            pushed.append(g)
+        st.dump_wait(n_gulps // every - 1)
+        stats = st.stats()
+        got = [hd[d].numpy().copy() for d in range(n_gulps // every)]
+    print("pushed", pushed, "stats", stats, flush=True)
+    assert stats["gulps"] == n_gulps
+    assert stats["correlated"] == len(pushed) and stats["dropped"] == n_gulps - len(pushed)
+    assert stats["dropped"] > 0, "the slow producer should have made some gulps late"
+    for d in range(n_gulps // every):
+        gs = [g for g in pushed if d * every <= g < (d + 1) * every]
+        acc = np.zeros((F, N * (N + 1) // 2, 2), np.int64)
+        for g in gs:
+            x, _, _ = synth.stream(seed, T, F, N, 4, sigma, t0=g * T, tone=tone)
+            oracle_lib.accumulate(acc, x, 4)
+        assert np.array_equal(got[d], oracle_lib.narrow(acc)), d
