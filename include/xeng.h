@@ -393,7 +393,9 @@ int xeng_stream_destroy(xeng_stream *s);
  * writes every valid packet's samples into the gulp buffer, zero-fills the
  * blocks whose packet did not arrive (zeros add nothing to any sum), and
  * counts received, missing, duplicate and rejected packets (bad magic, not
- * aligned to the blocks, or outside the gulp).
+ * aligned to the blocks, or outside the gulp). When several packets name
+ * the same block, the first in buffer order fills it and the others count
+ * as duplicates, whatever their payloads.
  */
 #define XENG_PACKET_MAGIC 0x4C454441u /* "LEDA" */
 
@@ -413,7 +415,7 @@ typedef struct {
 } xeng_ingest_stats;
 
 /* Create an ingest engine for gulps of `sub` (n_time samples) and packets of
- * `fmt`. Allocates a small device bitmap and counters. Errors: XENG_EINVAL
+ * `fmt`. Allocates a device table of 4 bytes per block and counters. Errors: XENG_EINVAL
  * (sizes that do not divide), XENG_ENOMEM, XENG_EHIP. */
 int xeng_ingest_create(const xeng_subarray *sub, const xeng_packet_format *fmt, xeng_ingest **out);
 
@@ -423,11 +425,13 @@ int xeng_ingest_packet_stride(const xeng_ingest *ig, int64_t *out);
 /* Scatter n_packets packets (device buffer, packet stride apart, any order)
  * into the device gulp buffer d_gulp for the gulp starting at absolute
  * time gulp_t0, zero-fill what is missing and update the counters; all
- * enqueued on hip_stream (a hipStream_t). d_gulp is fully written. */
+ * enqueued on hip_stream (a hipStream_t). d_gulp is fully written. The
+ * engine's table and counters serve one gulp at a time: a call on another
+ * stream than the previous call's waits for that call's work. */
 int xeng_ingest_gulp(xeng_ingest *ig, const void *d_packets, int64_t n_packets, int64_t gulp_t0,
                      void *d_gulp, void *hip_stream);
 
-/* Wait for the last gulp's ingest on its stream and return its counters. */
+/* Wait for the last gulp's ingest and return its counters. */
 int xeng_ingest_stats_get(xeng_ingest *ig, xeng_ingest_stats *out);
 
 /* Release the engine (waits for its last stream). NULL is a no-op. */

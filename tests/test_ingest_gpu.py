@@ -94,3 +94,61 @@ def test_ingest_errors(torch_cuda):
     with pytest.raises(XengError) as ei:
         Ingest(dict(n_inputs=48, n_chans=6, n_time=32), 3, 3, 4)   # 3 does not divide 32
     assert ei.value.code == XENG_EINVAL
+
+
+def test_ingest_duplicates_with_different_payloads(torch_cuda):
+    # retransmitted blocks whose payloads differ: the first copy in buffer
+    # order fills the block (as the reference does), run after run
+    from paper_1411_3751_amd import Ingest
+    torch = torch_cuda
+    print("case ingest differing duplicates", flush=True)
+    T, F, N, fmt = 64, 8, 64, (4, 2, 32)
+    rng = np.random.default_rng(12)
+    s = rng.integers(0, 256, size=(T, F, N), dtype=np.uint8)
+    t0 = 5000
+    pk = synth.packetize(s, t0, *fmt, 4)
+    # three more copies of 40 blocks, each with its own random payload
+    extra = []
+    for _ in range(3):
+        e = pk[rng.choice(len(pk), 40, replace=False)].copy()
+        e[:, 16:] = rng.integers(0, 256, size=e[:, 16:].shape, dtype=np.uint8)
+        extra.append(e)
+    allp = np.concatenate([pk] + extra)
+    allp = np.ascontiguousarray(allp[rng.permutation(len(allp))])
+    want, wst = depacketize(allp, T, F, N, 4, t0, *fmt)
+    assert wst["duplicate"] == 120
+    sub = dict(n_inputs=N, n_chans=F, n_time=T)
+    d_pk = torch.from_numpy(allp.reshape(-1)).cuda()
+    with Ingest(sub, *fmt) as ig:
+        for rep in range(3):
+            out = torch.full((T, F, N), 0x55, dtype=torch.uint8, device="cuda")
+            ig.gulp(d_pk, len(allp), t0, out)
+            assert np.array_equal(out.cpu().numpy(), want), rep
+            assert ig.stats() == wst
+
+
+def test_ingest_gulps_on_two_streams(torch_cuda):
+    # successive gulps of one engine on different streams are ordered: each
+    # gulp's counters and bytes are its own
+    from paper_1411_3751_amd import Ingest
+    torch = torch_cuda
+    print("case ingest two streams", flush=True)
+    T, F, N, fmt = 64, 8, 64, (4, 2, 32)
+    rng = np.random.default_rng(13)
+    sub = dict(n_inputs=N, n_chans=F, n_time=T)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    with Ingest(sub, *fmt) as ig:
+        for g in range(4):
+            s = rng.integers(0, 256, size=(T, F, N), dtype=np.uint8)
+            t0 = g * T
+            pk = make_packets(rng, s, t0, fmt, 4)
+            want, wst = depacketize(pk, T, F, N, 4, t0, *fmt)
+            st = streams[g % 2]
+            with torch.cuda.stream(st):
+                d_pk = torch.from_numpy(pk.reshape(-1)).to("cuda", non_blocking=False)
+                out = torch.empty((T, F, N), dtype=torch.uint8, device="cuda")
+            st.synchronize()
+            ig.gulp(d_pk, len(pk), t0, out, stream=st)
+            assert ig.stats() == wst
+            st.synchronize()
+            assert np.array_equal(out.cpu().numpy(), want)
