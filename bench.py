@@ -831,11 +831,12 @@ def xengine_bench(args):
     mhz = clock_under_load(step, max(8, int(12.0 / max(ms_step, 1e-3))))
 
     # kernel pass (after the timed region): an event pair on the stream
-    # around each correlate call times that launch of the tile kernel (with
-    # the one-wave kernel the step is that one launch, the dump fused in)
+    # around each launch of the tile kernel. With a tile kernel that fuses the
+    # dump and at most 32768 samples the step is that one launch; otherwise
+    # the pair brackets the correlate call and the dump runs outside it
     k_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
             for _ in range(n)]
-    fused = plan["subarrays"][0]["kernel"] == "one_wave"
+    fused = plan["subarrays"][0]["kernel"] != "register_staging" and T <= 32768
     for k in range(n):
         k_ev[k][0].record(stream)
         if fused:

@@ -15,6 +15,7 @@ SOURCES = [os.path.join(HERE, "csrc", "xeng.hip")]
 HEADERS = [os.path.join(HERE, "csrc", "xcorr_i8.h"), os.path.join(HERE, "csrc", "xcorr_wg.h"),
            os.path.join(HERE, "csrc", "xeng_stream.h"), os.path.join(HERE, "csrc", "xeng_tune.h"),
            os.path.join(HERE, "csrc", "xeng_ingest.h"), os.path.join(HERE, "csrc", "xeng_fengine.h"),
+           os.path.join(HERE, "csrc", "xcorr_w1.h"), os.path.join(HERE, "csrc", "xeng_static.h"),
            os.path.join(ROOT, "include", "xeng.h")]
 ARCH = "gfx950"
 
