@@ -161,15 +161,20 @@ int xeng_max_dump_samples(const xeng_ctx *ctx, int sub, int64_t *out);
  *   XENG_KERNEL_REGISTER   register-staging tiles of 32 x tile (any shape)
  *   XENG_KERNEL_PERSISTENT persistent 4-wave workgroups over 128 x 128 tiles
  *                          (N % 16 == 0 for 4-bit, N % 8 == 0 for 8-bit; the
- *                          only one for the FP8 engine; the default)
+ *                          only one for the FP8 engine)
+ *                          (the default for other shapes)
  *   XENG_KERNEL_ONE_WAVE   wave-private items of 128 x 64, one wave per SIMD
  *   XENG_KERNEL_TWO_WAVE   wave-private items of 64 x 64, two waves per SIMD
  *                          (both: 4-bit input, int8 engine, N % 16 == 0)
+ *   XENG_KERNEL_SMALL_N    one channel per item, 64 x 64 (4-bit input, int8
+ *                          engine, N <= 64 and N % 16 == 0: the memory-bound
+ *                          regime; the default for such shapes)
  */
 #define XENG_KERNEL_REGISTER 0
 #define XENG_KERNEL_PERSISTENT 1
 #define XENG_KERNEL_ONE_WAVE 2
 #define XENG_KERNEL_TWO_WAVE 3
+#define XENG_KERNEL_SMALL_N 4
 
 /*
  * Run subarray sub on kernel family `kernel` (tile: 32, 64 or 128 inputs for

@@ -39,6 +39,7 @@
 #include "xcorr_i8.h"
 #include "xcorr_w1.h"
 #include "xcorr_wg.h"
+#include "xcorr_sn.h"
 
 namespace {
 
@@ -76,7 +77,8 @@ struct Sub {
     bool acc_zero = true;      // accumulator logically zero (next launch overwrites)
     bool wave = false;         // handled by a persistent kernel (one launch per group)
     bool w1 = false;           // ... a wave-private one
-    int wv = 0;                // which one: 1 (one wave per SIMD) or 2 (two)
+    int wv = 0;                // which one: 1 (one wave per SIMD) or 2 (two); 3: the
+                               // small-N kernel (one channel per item)
     int wt = 4;                // register kernel: wave tile edge in 16-row sub-blocks
     int bt = 128;              // register kernel: workgroup tile edge
     int n_tiles = 0;           // register kernel: tiles per channel
@@ -100,7 +102,7 @@ struct WavePlan {
     int engine = XENG_ENGINE_I8;     // every subarray of a plan uses this engine
     int in_bits = 4;                 // and this input width
     bool w1 = false;                 // wave-private kernel (items per wave) or 4-wave kernel (tiles)
-    int wv = 0;                      // wave-private kernel: 1 or 2 waves per SIMD
+    int wv = 0;                      // wave-private kernel: 1 or 2 waves per SIMD; 3: small-N kernel
     std::vector<int> subs;           // context subarray indices, in launch order
     std::vector<xeng::WgItem> items; // flat, grouped per workgroup
     std::vector<int32_t> wg_begin;   // [n_wg + 1]
@@ -157,6 +159,14 @@ bool wave_path(const xeng_subarray &c)
 bool w1_path(const xeng_subarray &c)
 {
     return c.in_bits == 4 && c.engine == XENG_ENGINE_I8 && c.n_inputs % 16 == 0;
+}
+
+// Small-N kernel: 4-bit input, int8 engine, at most 64 inputs in 16-byte
+// chunks, 256-row stages whose byte offsets fit 32 bits.
+bool sn_path(const xeng_subarray &c)
+{
+    return c.in_bits == 4 && c.engine == XENG_ENGINE_I8 && c.n_inputs <= xeng::SN_MAX_N &&
+           c.n_inputs % 16 == 0 && (int64_t)c.n_chans * c.n_inputs * xeng::SN_TKS < ((int64_t)1 << 31);
 }
 
 int choose_wt(int n_inputs)
@@ -239,7 +249,20 @@ void build_schedule(WavePlan &p, const std::vector<Sub> &subs, int n_cu, int wg_
                         all.push_back(it);
                     }
     }
-    for (size_t k = 0; k < p.subs.size() && !p.w1; ++k) {
+    for (size_t k = 0; k < p.subs.size() && p.wv == 3; ++k) {
+        // small-N kernel: one item per channel, one stage loop per 256 samples
+        const Sub &s = subs[p.subs[k]];
+        const int nst = (s.cfg.n_time + xeng::SN_TKS - 1) / xeng::SN_TKS;
+        const int segs = (s.cfg.n_time + xeng::SEG_T - 1) / xeng::SEG_T;
+        for (int f = 0; f < s.cfg.n_chans; ++f) {
+            It it;
+            it.w.cs = (uint32_t)f | ((uint32_t)k << 24);
+            it.w.ij = 0;
+            it.cost = (double)nst / segs + 4.0;
+            all.push_back(it);
+        }
+    }
+    for (size_t k = 0; k < p.subs.size() && !p.w1 && p.wv != 3; ++k) {
         const Sub &s = subs[p.subs[k]];
         const int nb = (s.cfg.n_inputs + 127) / 128;
         const int tks = s.cfg.in_bits == 4 ? xeng::WgGeom<4>::TKS : xeng::WgGeom<8>::TKS;
@@ -430,7 +453,10 @@ int launch_wave(xeng_ctx *ctx, WavePlan &p, const void *const *d_samples, void *
         // sums; the others leave the raw form in the accumulator
         const bool fuse = last && out;
         const dim3 g(p.n_wg), b(xeng::WG_THREADS);
-        if (p.engine == XENG_ENGINE_FP8) {
+        if (p.wv == 3) {
+            if (fuse) hipLaunchKernelGGL((xeng::xcorr_sn_kernel<true>), g, b, 0, ctx->stream, a);
+            else hipLaunchKernelGGL((xeng::xcorr_sn_kernel<false>), g, b, 0, ctx->stream, a);
+        } else if (p.engine == XENG_ENGINE_FP8) {
             if (fuse) hipLaunchKernelGGL((xeng::xcorr_wg_kernel<xeng::ENG_F8, 4, true>), g, b, 0, ctx->stream, a);
             else hipLaunchKernelGGL((xeng::xcorr_wg_kernel<xeng::ENG_F8, 4, false>), g, b, 0, ctx->stream, a);
         } else if (p.in_bits == 4) {
@@ -475,8 +501,8 @@ int replan(xeng_ctx *ctx)
         s.n_tiles = nb * (nb + 1) / 2;
     }
     // (engine, input width, wave-private kernel variant)
-    const int kinds[5][3] = {{XENG_ENGINE_I8, 4, 1}, {XENG_ENGINE_I8, 4, 2}, {XENG_ENGINE_I8, 4, 0},
-                             {XENG_ENGINE_I8, 8, 0}, {XENG_ENGINE_FP8, 4, 0}};
+    const int kinds[6][3] = {{XENG_ENGINE_I8, 4, 3}, {XENG_ENGINE_I8, 4, 1}, {XENG_ENGINE_I8, 4, 2},
+                             {XENG_ENGINE_I8, 4, 0}, {XENG_ENGINE_I8, 8, 0}, {XENG_ENGINE_FP8, 4, 0}};
     for (const auto &kd : kinds) {
         std::vector<int> es;
         bool one_group = true;
@@ -496,7 +522,7 @@ int replan(xeng_ctx *ctx)
             ctx->plans.emplace_back();
             ctx->plans.back().engine = kd[0];
             ctx->plans.back().in_bits = kd[1];
-            ctx->plans.back().w1 = kd[2] != 0;
+            ctx->plans.back().w1 = kd[2] == 1 || kd[2] == 2;
             ctx->plans.back().wv = kd[2];
             ctx->plans.back().subs = g;
         }
@@ -519,8 +545,8 @@ struct SubKey {
     }
 };
 // Kernel families: register-staging tiles, the persistent 4-wave kernel, the
-// wave-private kernel with one or two waves per SIMD.
-constexpr int FAM_REG = 0, FAM_WG = 1, FAM_W1 = 2, FAM_W2 = 3;
+// wave-private kernel with one or two waves per SIMD, the small-N kernel.
+constexpr int FAM_REG = 0, FAM_WG = 1, FAM_W1 = 2, FAM_W2 = 3, FAM_SN = 4;
 struct SubChoice {
     int fam;
     int wt;
@@ -550,10 +576,11 @@ void set_choice(Sub &s, int fam, int wt)
 {
     if (s.cfg.engine == XENG_ENGINE_FP8) fam = FAM_WG;
     if ((fam == FAM_W1 || fam == FAM_W2) && !w1_path(s.cfg)) fam = FAM_WG;
+    if (fam == FAM_SN && !sn_path(s.cfg)) fam = FAM_WG;
     if (fam == FAM_WG && !wave_path(s.cfg)) fam = FAM_REG;
     s.wave = fam != FAM_REG;
     s.w1 = fam == FAM_W1 || fam == FAM_W2;
-    s.wv = fam == FAM_W1 ? 1 : (fam == FAM_W2 ? 2 : 0);
+    s.wv = fam == FAM_W1 ? 1 : (fam == FAM_W2 ? 2 : (fam == FAM_SN ? 3 : 0));
     s.wt = wt;
     s.bt = 32 * wt;
     // the register-staging launch's grid follows the tile size
@@ -563,13 +590,16 @@ void set_choice(Sub &s, int fam, int wt)
 
 const char *fam_name(int fam)
 {
-    return fam == FAM_W1 ? "one_wave"
-                         : (fam == FAM_W2 ? "two_wave" : (fam == FAM_WG ? "persistent_workgroup" : "register_staging"));
+    return fam == FAM_W1   ? "one_wave"
+           : fam == FAM_W2 ? "two_wave"
+           : fam == FAM_SN ? "small_n"
+           : fam == FAM_WG ? "persistent_workgroup"
+                           : "register_staging";
 }
 
 int fam_of(const Sub &s)
 {
-    return s.wv == 1 ? FAM_W1 : (s.wv == 2 ? FAM_W2 : (s.wave ? FAM_WG : FAM_REG));
+    return s.wv == 1 ? FAM_W1 : (s.wv == 2 ? FAM_W2 : (s.wv == 3 ? FAM_SN : (s.wave ? FAM_WG : FAM_REG)));
 }
 
 void apply_tuning_cache(xeng_ctx *ctx)
@@ -700,7 +730,7 @@ int xeng_create(const xeng_subarray *subs, int n_subs, void *hip_stream, xeng_ct
         s.cfg = subs[k];
         s.tri = (int64_t)s.cfg.n_inputs * (s.cfg.n_inputs + 1) / 2;
         s.max_dump = s.cfg.in_bits == 4 ? XENG_MAX_DUMP_SAMPLES_4BIT : XENG_MAX_DUMP_SAMPLES_8BIT;
-        set_choice(s, FAM_WG, choose_wt(s.cfg.n_inputs));
+        set_choice(s, sn_path(s.cfg) ? FAM_SN : FAM_WG, choose_wt(s.cfg.n_inputs));
         const int nb = (s.cfg.n_inputs + s.bt - 1) / s.bt;
         s.n_tiles = nb * (nb + 1) / 2;
         const size_t bytes = (size_t)s.tri * (size_t)s.cfg.n_chans * 8;
@@ -880,14 +910,15 @@ int xeng_set_kernel(xeng_ctx *ctx, int sub, int kernel, int tile)
 {
     if (!ctx) return fail(XENG_EINVAL, "ctx is NULL");
     if (sub < 0 || sub >= (int)ctx->subs.size()) return fail(XENG_EINVAL, "sub %d out of range", sub);
-    if (kernel < XENG_KERNEL_REGISTER || kernel > XENG_KERNEL_TWO_WAVE)
+    if (kernel < XENG_KERNEL_REGISTER || kernel > XENG_KERNEL_SMALL_N)
         return fail(XENG_EINVAL, "unknown kernel family %d", kernel);
     if (kernel == XENG_KERNEL_REGISTER && tile != 32 && tile != 64 && tile != 128)
         return fail(XENG_EINVAL, "register-staging tile %d is not 32, 64 or 128", tile);
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     const int fam = kernel == XENG_KERNEL_REGISTER ? FAM_REG
                     : kernel == XENG_KERNEL_PERSISTENT ? FAM_WG
-                    : kernel == XENG_KERNEL_ONE_WAVE ? FAM_W1 : FAM_W2;
+                    : kernel == XENG_KERNEL_ONE_WAVE ? FAM_W1
+                    : kernel == XENG_KERNEL_TWO_WAVE ? FAM_W2 : FAM_SN;
     Sub &s = ctx->subs[sub];
     set_choice(s, fam, kernel == XENG_KERNEL_REGISTER ? tile / 32 : s.wt);
     int rc = replan(ctx);
@@ -933,7 +964,7 @@ int xeng_plan_describe(const xeng_ctx *ctx, char *buf, size_t len)
                      "\"launches_per_call\": %lld}",
                      k ? ", " : "", s.cfg.n_inputs, s.cfg.n_chans, s.cfg.n_time, s.cfg.in_bits,
                      s.cfg.engine == XENG_ENGINE_I8 ? "i8" : "fp8", fam_name(fam_of(s)),
-                     s.wv == 2 ? 64 : 128, (long long)segs);
+                     s.wv == 2 || s.wv == 3 ? 64 : 128, (long long)segs);
         else
             snprintf(item, sizeof item,
                      "%s{\"n_inputs\": %d, \"n_chans\": %d, \"n_time\": %d, \"in_bits\": %d, "
@@ -955,7 +986,7 @@ int xeng_plan_describe(const xeng_ctx *ctx, char *buf, size_t len)
         snprintf(item, sizeof item,
                  "%s{\"kernel\": \"%s\", \"subarrays\": %zu, \"items\": %zu, \"workgroups\": %d, "
                  "\"balance\": %.4f}",
-                 q ? ", " : "", p.wv == 1 ? "one_wave" : (p.wv == 2 ? "two_wave" : "persistent_workgroup"),
+                 q ? ", " : "", fam_name(p.wv == 1 ? FAM_W1 : (p.wv == 2 ? FAM_W2 : (p.wv == 3 ? FAM_SN : FAM_WG))),
                  p.subs.size(),
                  p.items.size(), p.n_wg,
                  p.max_wg_cost > 0 ? p.mean_wg_cost / p.max_wg_cost : 1.0);

@@ -128,6 +128,7 @@ int xeng_autotune(xeng_ctx *ctx, const void *const *d_samples, int reps)
             cands.push_back({FAM_W2, 4});
             cands.push_back({FAM_W1, 4});
         }
+        if (sn_path(s.cfg)) cands.push_back({FAM_SN, 4});
         if (wave_path(s.cfg)) cands.push_back({FAM_WG, 4});
         const int N = s.cfg.n_inputs;
         if (N <= 128) cands.push_back({FAM_REG, 1});
@@ -143,7 +144,9 @@ int xeng_autotune(xeng_ctx *ctx, const void *const *d_samples, int reps)
             tune_note(ctx, "{\"step\": \"alone\", \"sub\": %zu, \"kernel\": \"%s\", \"tile\": %d, "
                            "\"ms\": %.4f}",
                       k, fam_name(cands[q].fam),
-                      cands[q].fam == FAM_REG ? 32 * cands[q].wt : (cands[q].fam == FAM_W2 ? 64 : 128), ms);
+                      cands[q].fam == FAM_REG ? 32 * cands[q].wt
+                                              : (cands[q].fam == FAM_W2 || cands[q].fam == FAM_SN ? 64 : 128),
+                      ms);
             if (q == 0 || ms < best) {
                 best = ms;
                 pick = cands[q];

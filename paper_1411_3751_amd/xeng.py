@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libxeng.so")
 
 XENG_OK, XENG_EINVAL, XENG_ERANGE, XENG_ENOMEM, XENG_EHIP, XENG_EBUSY = 0, 1, 2, 3, 4, 5
-KERNEL_REGISTER, KERNEL_PERSISTENT, KERNEL_ONE_WAVE, KERNEL_TWO_WAVE = 0, 1, 2, 3
+KERNEL_REGISTER, KERNEL_PERSISTENT, KERNEL_ONE_WAVE, KERNEL_TWO_WAVE, KERNEL_SMALL_N = 0, 1, 2, 3, 4
 ENGINE_I8, ENGINE_FP8 = 0, 1
 MAX_DUMP_SAMPLES_4BIT = 16777215
 MAX_DUMP_SAMPLES_8BIT = 65535

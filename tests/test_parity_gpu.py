@@ -220,7 +220,7 @@ def test_correlate_dump_one_call(torch_cuda, oracle_lib):
             assert np.array_equal(o, want), (N, T, bits)
 
 
-@pytest.mark.parametrize("kernel", [0, 1, 2, 3])
+@pytest.mark.parametrize("kernel", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("N,F,T", [(48, 3, 100), (144, 2, 333), (256, 2, 70000), (512, 1, 257)])
 def test_every_kernel_family(torch_cuda, oracle_lib, kernel, N, F, T):
     # each kernel family pinned with xeng_set_kernel: two calls then a dump,
@@ -245,3 +245,39 @@ def test_every_kernel_family(torch_cuda, oracle_lib, kernel, N, F, T):
         assert np.array_equal(got, oracle_lib.narrow(wa + wb))
         got = c.correlate_dump([db])[0].cpu().numpy()
         assert np.array_equal(got, oracle_lib.narrow(wb))
+
+
+@pytest.mark.parametrize("N,F,T", [(64, 5, 100), (64, 1030, 513), (64, 2, 70000), (32, 3, 256),
+                                   (16, 7, 1), (48, 4, 1000), (64, 600, 4096)])
+def test_small_n_kernel(torch_cuda, oracle_lib, N, F, T):
+    # the small-N kernel (one channel per item, the default for 4-bit N <= 64):
+    # ragged and whole stages, several channels per workgroup (F above the
+    # resident workgroups), several segments, accumulate then correlate-and-dump
+    from paper_1411_3751_amd import Correlator
+    torch = torch_cuda
+    print("case small_n N=%d F=%d T=%d" % (N, F, T), flush=True)
+    rng = np.random.default_rng(7000 + N + F + T)
+    a = rand_stream(rng, T, F, N, 4)
+    b = rand_stream(rng, T, F, N, 4)
+    da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    # full oracle on a channel sample when F is large (first, last, seeded)
+    chans = None if F <= 16 else sorted({0, F - 1, *rng.choice(F, 6, replace=False).tolist()})
+    wa = oracle_lib.correlate(a, 4, chans=chans)
+    wb = oracle_lib.correlate(b, 4, chans=chans)
+    pick = (lambda v: v) if chans is None else (lambda v: v[chans])
+    with Correlator([dict(n_inputs=N, n_chans=F, n_time=T)]) as c:
+        assert c.plan()["subarrays"][0]["kernel"] == "small_n"
+        c.correlate([da])
+        c.correlate([db])
+        assert np.array_equal(pick(c.dump()[0].cpu().numpy()), oracle_lib.narrow(wa + wb))
+        c.correlate([db])
+        got = c.correlate_dump([da])[0].cpu().numpy()
+        assert np.array_equal(pick(got), oracle_lib.narrow(wa + wb))
+        got = c.correlate_dump([db])[0].cpu().numpy()
+        assert np.array_equal(pick(got), oracle_lib.narrow(wb))
+        if chans is not None:
+            # every channel by the projection check
+            wrng = np.random.default_rng(7100 + N + F)
+            for f in range(F):
+                w = wrng.integers(-4, 5, size=(N, 2)).astype(np.int64)
+                assert oracle_lib.projection_check(b, 4, f, got[f], w) == 0, f
