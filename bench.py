@@ -34,6 +34,7 @@ PROFILES = os.path.join(ROOT, "profiles")
 # uses); host-only changes elsewhere do not invalidate them
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1411_3751_amd", "csrc", f)
                   for f in ("xcorr_wg.h", "xcorr_i8.h")]
+SN_SOURCES = ["xcorr_sn.h", "xcorr_wg.h", "xcorr_i8.h"]  # the small-N kernel and its helpers
 
 
 def kernel_source_hash(files=None) -> str:
@@ -896,10 +897,11 @@ def xengine_bench(args):
         res["clock_source"] = ("amdsmi gpu_metrics current_gfxclks, mean over XCDs, median of "
                                "readings between batches of the same steps after the timed region")
     if small:
+        sn = plan["subarrays"][0]["kernel"] == "small_n"
         res["roofline"] = {"bound": "hbm", "achieved": round(hbm_bytes / (ms_kernel * 1e-3) / 1e9, 1),
                            "peak": PEAK_HBM_GBS, "unit": "GB/s",
                            "frac": round(hbm_bytes / (ms_kernel * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
-                           "traffic": None}
+                           "traffic": hbm_traffic("xcorr_sn_kernel", name, SN_SOURCES) if sn else None}
     else:
         res["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                            "unit": "TFLOP/s", "frac": round(achieved / peak, 4),

@@ -220,17 +220,43 @@ int xeng_dump_fast_autos(xeng_ctx *ctx, void *const *out, int out_is_device, int
  * persistent launch per engine and input width).
  *
  * Time, on the caller's sample buffers d_samples[s] (as for xeng_correlate),
- * every kernel family that can run each subarray (the persistent kernel with
- * 128 x 128 tiles; the register-staging kernel with 32, 64 or 128-input
+ * every kernel family that can run each subarray (XENG_KERNEL_*: the
+ * persistent kernel with 128 x 128 tiles, the wave-private kernels, the
+ * small-N kernel, the register-staging kernel with 32, 64 or 128-input
  * tiles), each alone, `reps` runs each, and keep the fastest; then time the
  * batched launch's schedule options (1 or 2 workgroups per CU, tiles in
- * locality order or costliest first) and keep the fastest. The choices are
- * applied to ctx and remembered for this process: later contexts with the
- * same subarray shapes start with them. Any accumulated sums are discarded
- * (the context is left reset). Blocks until done. Errors: XENG_EINVAL,
- * XENG_EHIP.
+ * locality order or costliest first) and keep the fastest, and whole steps
+ * with every subarray the persistent kernel can run moved into one launch.
+ * The choices are applied to ctx and remembered for this process, keyed by
+ * (device architecture, n_inputs, n_chans, n_time, in_bits, engine) per
+ * subarray and per list of subarrays: later contexts with the same shapes on
+ * the same architecture start with them. With the environment variable
+ * XENG_TUNING_FILE set, the whole cache is then written to that file (see
+ * xeng_tuning_save). Any accumulated sums are discarded (the context is left
+ * reset). Blocks until done. Errors: XENG_EINVAL, XENG_EHIP.
  */
 int xeng_autotune(xeng_ctx *ctx, const void *const *d_samples, int reps);
+
+/*
+ * The process's tuning cache as a JSON file: {"format": "xeng-tuning",
+ * "version": 1, "subarrays": [...], "batches": [...]}, one entry per tuned
+ * shape (keys as above, the kernel family by its plan-JSON name and its tile
+ * edge) and per tuned list of shapes (kernels, workgroups per CU, tile
+ * order). Entries of every architecture are kept; only the current device's
+ * are applied. xeng_tuning_save writes the whole cache to `path` (through a
+ * temporary file renamed over it); xeng_tuning_load merges a file into the
+ * cache (all or nothing: a file that does not parse changes nothing).
+ * *n_entries (if not NULL) receives the number of entries written or read.
+ * With XENG_TUNING_FILE set, the first xeng_create of the process loads that
+ * file if it exists (and ignores it if it does not parse). These calls touch
+ * no device. Errors: XENG_EINVAL (NULL path, unreadable or unwritable file,
+ * malformed content).
+ */
+int xeng_tuning_save(const char *path, int *n_entries);
+int xeng_tuning_load(const char *path, int *n_entries);
+/* Forget every tuning choice of this process (contexts already created keep
+ * theirs). Returns XENG_OK. */
+int xeng_tuning_clear(void);
 
 typedef struct xeng_graph xeng_graph; /* opaque, library-owned */
 

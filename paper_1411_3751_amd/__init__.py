@@ -14,6 +14,10 @@ from .xeng import (  # noqa: F401
     Stream,
     Subarray,
     XengError,
+    correlate_dump_static,
     load,
     tri,
+    tuning_clear,
+    tuning_load,
+    tuning_save,
 )

@@ -37,7 +37,7 @@ namespace xeng {
 constexpr int SN_ROWB = 64;                       // bytes per staged row (64 inputs)
 constexpr int SN_TKS = WG_STAGE / SN_ROWB;        // time rows per stage (256)
 constexpr int SN_KS = SN_TKS / 32;                // K steps per stage (8)
-constexpr int SN_NBUF = 4;                        // ring depth
+constexpr int SN_NBUF = 4;                        // ring depth (5 measured slower)
 constexpr int SN_DMA = WG_STAGE / (WG_THREADS * 16); // 16-byte copies per thread per stage (4)
 constexpr int SN_MAX_N = 64;
 

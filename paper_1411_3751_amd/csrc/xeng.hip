@@ -125,6 +125,7 @@ struct xeng_ctx {
     hipStream_t stream = nullptr;
     int device = 0;
     int n_cu = 0;
+    std::string arch;                // device architecture ("gfx950"): part of the tuning keys
     uint32_t *d_stage = nullptr;  // device staging for host dumps
     size_t stage_words = 0;
 };
@@ -554,11 +555,15 @@ struct SubChoice {
 struct SchedChoice {
     int wg_per_cu, order;
 };
+// Keys carry the device architecture: choices measured on one chip are not
+// applied on another.
+using ArchKey = std::pair<std::string, SubKey>;
+using ArchSet = std::pair<std::string, std::vector<SubKey>>;
 std::mutex g_tune_mu;
-std::map<SubKey, SubChoice> g_tune_sub;
-std::map<std::vector<SubKey>, SchedChoice> g_tune_sched;
+std::map<ArchKey, SubChoice> g_tune_sub;
+std::map<ArchSet, SchedChoice> g_tune_sched;
 // per set of shapes: the choices of a batch tuned as a whole
-std::map<std::vector<SubKey>, std::vector<SubChoice>> g_tune_set;
+std::map<ArchSet, std::vector<SubChoice>> g_tune_set;
 
 SubKey key_of(const xeng_subarray &c) { return SubKey{c.n_inputs, c.n_chans, c.n_time, c.in_bits, c.engine}; }
 
@@ -606,13 +611,13 @@ void apply_tuning_cache(xeng_ctx *ctx)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     bool all = true;
-    auto set_it = g_tune_set.find(keys_of(ctx));
+    auto set_it = g_tune_set.find(ArchSet{ctx->arch, keys_of(ctx)});
     if (set_it != g_tune_set.end()) {
         for (size_t k = 0; k < ctx->subs.size(); ++k)
             set_choice(ctx->subs[k], set_it->second[k].fam, set_it->second[k].wt);
     } else {
         for (Sub &s : ctx->subs) {
-            auto it = g_tune_sub.find(key_of(s.cfg));
+            auto it = g_tune_sub.find(ArchKey{ctx->arch, key_of(s.cfg)});
             if (it == g_tune_sub.end()) {
                 all = false;
                 continue;
@@ -620,7 +625,7 @@ void apply_tuning_cache(xeng_ctx *ctx)
             set_choice(s, it->second.fam, it->second.wt);
         }
     }
-    auto it = g_tune_sched.find(keys_of(ctx));
+    auto it = g_tune_sched.find(ArchSet{ctx->arch, keys_of(ctx)});
     if (it != g_tune_sched.end()) {
         ctx->wg_per_cu = it->second.wg_per_cu;
         ctx->order = it->second.order;
@@ -703,6 +708,14 @@ int xeng_dump_fast_autos(xeng_ctx *ctx, void *const *out, int out_is_device, int
     return XENG_OK;
 }
 
+} // extern "C"
+namespace {
+std::string device_arch(int dev);
+void tuning_file_autoload();
+void tuning_file_autosave();
+} // namespace
+extern "C" {
+
 int xeng_create(const xeng_subarray *subs, int n_subs, void *hip_stream, xeng_ctx **out)
 {
     if (!out) return fail(XENG_EINVAL, "out is NULL");
@@ -724,6 +737,8 @@ int xeng_create(const xeng_subarray *subs, int n_subs, void *hip_stream, xeng_ct
         delete ctx;
         return fail(XENG_EHIP, "cannot query the current HIP device");
     }
+    ctx->arch = device_arch(ctx->device);
+    tuning_file_autoload();
     ctx->subs.resize(n_subs);
     for (int k = 0; k < n_subs; ++k) {
         Sub &s = ctx->subs[k];
@@ -1002,6 +1017,7 @@ int xeng_plan_describe(const xeng_ctx *ctx, char *buf, size_t len)
 
 #include "xeng_stream.h"
 #include "xeng_tune.h"
+#include "xeng_tuning_file.h"
 #include "xeng_ingest.h"
 #include "xeng_fengine.h"
 #include "xeng_static.h"

@@ -242,13 +242,15 @@ int xeng_autotune(xeng_ctx *ctx, const void *const *d_samples, int reps)
     }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        for (size_t k = 0; k < ctx->subs.size(); ++k) g_tune_sub[key_of(ctx->subs[k].cfg)] = alone[k];
+        for (size_t k = 0; k < ctx->subs.size(); ++k)
+            g_tune_sub[ArchKey{ctx->arch, key_of(ctx->subs[k].cfg)}] = alone[k];
         std::vector<SubChoice> chosen;
         for (const Sub &s : ctx->subs) chosen.push_back(SubChoice{fam_of(s), s.wt});
-        g_tune_set[keys_of(ctx)] = chosen;
-        g_tune_sched[keys_of(ctx)] = SchedChoice{bw, bo};
+        g_tune_set[ArchSet{ctx->arch, keys_of(ctx)}] = chosen;
+        g_tune_sched[ArchSet{ctx->arch, keys_of(ctx)}] = SchedChoice{bw, bo};
     }
     ctx->tuned = true;
+    tuning_file_autosave();
     return XENG_OK;
 }
 

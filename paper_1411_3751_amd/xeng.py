@@ -31,6 +31,7 @@ EXPORTS = (
     "xeng_stream_drop", "xeng_stream_set_nonblocking", "xeng_stream_stats",
     "xeng_stream_set_fast_autos", "xeng_stream_fast_wait",
     "xeng_autotune", "xeng_graph_create", "xeng_graph_launch", "xeng_graph_destroy",
+    "xeng_tuning_save", "xeng_tuning_load", "xeng_tuning_clear",
     "xeng_set_fast_autos", "xeng_dump_fast_autos",
     "xeng_ingest_create", "xeng_ingest_packet_stride", "xeng_ingest_gulp", "xeng_ingest_stats_get",
     "xeng_ingest_destroy",
@@ -86,6 +87,13 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libxeng.so is not built (%s); run python -m paper_1411_3751_amd.build"
                           % LIB_PATH)
+    # PyTorch first: libxeng.so and torch then share the HIP runtime torch
+    # loads (the same soname); loaded the other way round, torch would run on
+    # the one libxeng.so found first
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
     pp = ctypes.POINTER(ctypes.c_void_p)
@@ -174,6 +182,12 @@ def load():
     lib.xeng_graph_launch.restype = i32
     lib.xeng_graph_destroy.argtypes = [vp]
     lib.xeng_graph_destroy.restype = i32
+    lib.xeng_tuning_save.argtypes = [ctypes.c_char_p, ctypes.POINTER(i32)]
+    lib.xeng_tuning_save.restype = i32
+    lib.xeng_tuning_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(i32)]
+    lib.xeng_tuning_load.restype = i32
+    lib.xeng_tuning_clear.argtypes = []
+    lib.xeng_tuning_clear.restype = i32
     _lib = lib
     return lib
 
@@ -203,6 +217,29 @@ def _ptrs(values):
     for k, v in enumerate(values):
         arr[k] = v
     return arr
+
+
+def tuning_save(path) -> int:
+    """xeng_tuning_save: write this process's tuning choices to a JSON file;
+    returns the number of entries written."""
+    lib = load()
+    n = ctypes.c_int32(0)
+    _check(lib.xeng_tuning_save(os.fsencode(path), ctypes.byref(n)))
+    return n.value
+
+
+def tuning_load(path) -> int:
+    """xeng_tuning_load: merge a tuning file into this process's choices;
+    returns the number of entries read."""
+    lib = load()
+    n = ctypes.c_int32(0)
+    _check(lib.xeng_tuning_load(os.fsencode(path), ctypes.byref(n)))
+    return n.value
+
+
+def tuning_clear():
+    """xeng_tuning_clear: forget this process's tuning choices."""
+    _check(load().xeng_tuning_clear())
 
 
 def correlate_dump_static(subarray, samples, out, stream=None):

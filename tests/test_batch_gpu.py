@@ -119,3 +119,50 @@ def test_graph_survives_autotune(torch_cuda, oracle_lib):
                 for (N, F, T), h, o in zip(shapes, host, out):
                     want = oracle_lib.narrow(oracle_lib.correlate(h, 4))
                     assert np.array_equal(o.cpu().numpy(), want), (rep, N)
+
+
+def test_second_process_starts_tuned(torch_cuda, tmp_path):
+    # this process autotunes with XENG_TUNING_FILE set (the cache is written
+    # to the file); a fresh process with the same setting creates a context of
+    # the same shapes and starts with the same choices, marked tuned
+    import json
+    import os
+    import subprocess
+    import sys
+    from paper_1411_3751_amd import Correlator
+    torch = torch_cuda
+    path = str(tmp_path / "tuning.json")
+    shapes = [(64, 40, 2048), (256, 12, 2048), (144, 6, 1000)]
+    subs = [dict(n_inputs=N, n_chans=F, n_time=T) for N, F, T in shapes]
+    rng = np.random.default_rng(4242)
+    dev = [torch.from_numpy(rng.integers(0, 256, size=(T, F, N), dtype=np.uint8)).cuda()
+           for N, F, T in shapes]
+    os.environ["XENG_TUNING_FILE"] = path
+    try:
+        with Correlator(subs) as c:
+            c.autotune(dev, reps=1)
+            plan = c.plan()
+    finally:
+        del os.environ["XENG_TUNING_FILE"]
+    picks = [s["kernel"] for s in plan["subarrays"]]
+    print("process 1 picks", picks, flush=True)
+    doc = json.load(open(path))
+    assert doc["format"] == "xeng-tuning"
+    # (earlier tests of this process may have tuned other shape lists)
+    mine = [b for b in doc["batches"] if b["shapes"] == [[N, F, T, 4, 0] for N, F, T in shapes]]
+    assert len(mine) == 1 and [k for k, _ in mine[0]["kernels"]] == picks
+    code = ("import json; from paper_1411_3751_amd import Correlator\n"
+            "subs = %r\n"
+            "with Correlator(subs) as c:\n"
+            "    p = c.plan()\n"
+            "print(json.dumps({'tuned': p['tuned'], 'picks': [s['kernel'] for s in p['subarrays']],"
+            " 'wg': p['workgroups_per_cu'], 'order': p['schedule_order']}))\n" % subs)
+    env = dict(os.environ, XENG_TUNING_FILE=path)
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         timeout=300, cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert out.returncode == 0, out.stderr[-2000:]
+    got = json.loads(out.stdout.strip().splitlines()[-1])
+    print("process 2", got, flush=True)
+    assert got["tuned"] is True
+    assert got["picks"] == picks
+    assert got["wg"] == plan["workgroups_per_cu"] and got["order"] == plan["schedule_order"]
