@@ -23,9 +23,10 @@
 // and im bytes.
 //
 // Each wave computes a 64 x 64 quarter of the tile as 2 x 2 MFMA tiles of
-// 32 x 32. On a diagonal tile (J = I, only the I half is copied) three
-// quarters are needed: waves 0, 1 take the diagonal ones, wave 2 the lower
-// one, and wave 3 only copies and synchronises.
+// 32 x 32. On a diagonal tile (J = I, only the I half is copied) the lower
+// triangle is 10 such tiles: waves 0, 1 take the diagonal quarters less
+// their upper tile (3 each), waves 2, 3 the two 64 x 32 columns below the
+// first quarter (2 each).
 //
 // Operands: re, im and ~im (= -im - 1, so that -(-8) or -(-128) never has to
 // fit in int8); 4-bit values are scaled by 16 by the nibble masks (see
@@ -147,8 +148,10 @@ __device__ __forceinline__ u32x4 wg_raw(const WgRaw &R, int k, int sd, int blk)
 }
 
 // ... and S[x] += the real parts of its I-side words (row sums for the Im
-// correction): 4 v_dot8_i32_i4 with weights 1 on the real nibbles
-template <bool SUMS>
+// correction): 4 v_dot8_i32_i4 with weights 1 on the real nibbles. NY: the
+// J blocks the wave multiplies (2, or 1 for the column roles of a diagonal
+// tile).
+template <bool SUMS, int NY>
 __device__ __forceinline__ void wg_unpack(const WgRaw &R, int k, WgOps &o, int32_t (&S)[2])
 {
 #pragma unroll
@@ -162,7 +165,7 @@ __device__ __forceinline__ void wg_unpack(const WgRaw &R, int k, WgOps &o, int32
         }
     }
 #pragma unroll
-    for (int y = 0; y < 2; ++y) {
+    for (int y = 0; y < NY; ++y) {
         const u32x4 p = wg_raw(R, k, 1, y);
         const u32x4 im = (p << 4) & 0xF0F0F0F0u;
         o.reJ[y] = (i32x4)(p & 0xF0F0F0F0u);
@@ -188,7 +191,7 @@ __device__ __forceinline__ void wg8_split(const WgRaw &R, int sd, int blk, i32x4
     }
 }
 
-template <bool SUMS>
+template <bool SUMS, int NY>
 __device__ __forceinline__ void wg8_unpack(const WgRaw &R, WgOps &o, int32_t (&S)[2])
 {
 #pragma unroll
@@ -201,21 +204,22 @@ __device__ __forceinline__ void wg8_unpack(const WgRaw &R, WgOps &o, int32_t (&S
         }
     }
 #pragma unroll
-    for (int y = 0; y < 2; ++y) {
+    for (int y = 0; y < NY; ++y) {
         wg8_split(R, 1, y, o.reJ[y], o.imJ[y]);
         o.niJ[y] = ~o.imJ[y];
     }
 }
 
-// The MFMAs of blocks [b0, b1) of one K step, blocks in the order
-// (x, y) = (0, 0), (1, 0), (0, 1), (1, 1):
+// The MFMAs of blocks [b0, b1) of one K step that MASK names (bit b), blocks
+// in the order b = (x, y) = (0, 0), (1, 0), (0, 1), (1, 1):
 //   accR[x][y] += re_I re_J + im_I im_J,  accI[x][y] += re_I ~im_J + im_I re_J.
-template <int B0, int B1>
+template <int B0, int B1, int MASK>
 __device__ __forceinline__ void wg_mfma_blocks(const WgOps &o, i32x16 (&accR)[2][2],
                                                i32x16 (&accI)[2][2])
 {
 #pragma unroll
     for (int b = B0; b < B1; ++b) {
+        if (!((MASK >> b) & 1)) continue;
         const int x = b & 1, y = b >> 1;
         accR[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.reI[x], o.reJ[y], accR[x][y], 0, 0, 0);
         accI[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.reI[x], o.niJ[y], accI[x][y], 0, 0, 0);
@@ -230,14 +234,17 @@ __device__ __forceinline__ void wg_mfma_blocks(const WgOps &o, i32x16 (&accR)[2]
 // for 4-bit input (two K steps per stage), one block for 8-bit (one K step).
 template <int IN_BITS> constexpr int wg_split() { return IN_BITS == 4 ? 2 : 1; }
 
-// 16 v_mfma_i32_32x32x32_i8 of one K step over 2 x 2 tiles of 32 x 32:
+// The v_mfma_i32_32x32x32_i8 of one K step over the 2 x 2 tiles of 32 x 32
+// that MASK names:
 //   accR[x][y] += re_I re_J + im_I im_J,  accI[x][y] += re_I ~im_J + im_I re_J.
+template <int MASK>
 __device__ __forceinline__ void wg_mfma(const WgOps &o, i32x16 (&accR)[2][2], i32x16 (&accI)[2][2])
 {
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
+            if (!((MASK >> (x + 2 * y)) & 1)) continue;
             accR[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.reI[x], o.reJ[y], accR[x][y], 0, 0, 0);
             accI[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.reI[x], o.niJ[y], accI[x][y], 0, 0, 0);
             accR[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.imI[x], o.imJ[y], accR[x][y], 0, 0, 0);
@@ -307,6 +314,7 @@ __device__ __forceinline__ uint32_t wg_raw_dw(const WgRaw &R, int sd, int blk, i
 // One stage (64 samples) of the FP8 engine: 16 v_mfma_scale_f32_32x32x64_f8f6f4
 // (scales 2^0) over 2 x 2 tiles of 32 x 32:
 //   accR += re_I re_J + im_I im_J,  accI += im_I re_J + re_I (-im_J).
+template <int MASK>
 __device__ __forceinline__ void wg_f8_stage(const WgRaw &R, f32x16 (&accR)[2][2],
                                             f32x16 (&accI)[2][2])
 {
@@ -321,6 +329,7 @@ __device__ __forceinline__ void wg_f8_stage(const WgRaw &R, f32x16 (&accR)[2][2]
         }
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
+        if (!((MASK >> (2 * y)) & 3)) continue; // no block of this J column
         // the negated imaginary operand replaces the plain one in the same
         // registers once the plain one's products are issued
         i32x8 reJ, imJ;
@@ -332,6 +341,7 @@ __device__ __forceinline__ void wg_f8_stage(const WgRaw &R, f32x16 (&accR)[2][2]
         }
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
+            if (!((MASK >> (x + 2 * y)) & 1)) continue;
             accR[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(reI[x], reJ, accR[x][y],
                                                                          0, 0, 0, 127, 0, 127);
             accI[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(imI[x], reJ, accI[x][y],
@@ -342,8 +352,9 @@ __device__ __forceinline__ void wg_f8_stage(const WgRaw &R, f32x16 (&accR)[2][2]
         const i32x8 niJ = imJ ^ (int32_t)0x80808080u;
 #pragma unroll
         for (int x = 0; x < 2; ++x)
-            accI[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(reI[x], niJ, accI[x][y],
-                                                                         0, 0, 0, 127, 0, 127);
+            if ((MASK >> (x + 2 * y)) & 1)
+                accI[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(reI[x], niJ, accI[x][y],
+                                                                             0, 0, 0, 127, 0, 127);
     }
 }
 
@@ -445,30 +456,33 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
     for (int k = 0; k < WG_NBUF - 1; ++k)
         if (issued < n_total) d_issue();
 
-    // This wave's 64 x 64 quarter of tile w: its I inputs start at position
-    // ip, its J inputs at jp of the staged row (J half at 128), output origin
-    // (r0, c0). On a diagonal tile the J half is not copied (J = I): waves 0,
-    // 1 take the diagonal quarters, wave 2 the lower off-diagonal quarter,
-    // and wave 3 has none (write = false: it computes and writes nothing).
-    auto role = [&](const WgItem &w, int &ip, int &jp, int &r0, int &c0, bool &write) {
+    // This wave's part of tile w: its I inputs start at position ip, its J
+    // inputs at jp of the staged row (J half at 128), output origin (r0, c0).
+    // Off the diagonal (kind 0) each wave takes a 64 x 64 quarter. A diagonal
+    // tile (J = I, only the I half is copied) has 10 lower-triangle blocks of
+    // 32 x 32: waves 0 and 1 take the diagonal quarters without their upper
+    // block (kind 1, 3 blocks each), waves 2 and 3 the blocks of rows 64..127
+    // in columns 0..31 and 32..63 (kind 2, 2 blocks each).
+    auto role = [&](const WgItem &w, int &ip, int &jp, int &r0, int &c0, int &kind) {
         const int bi = (int)(w.ij & 0xFFFFu), bj = (int)(w.ij >> 16);
         const int I0 = 128 * bi, J0 = 128 * bj;
-        write = true;
         if (bi != bj) {
             const int wr = wave >> 1, wc = wave & 1;
             ip = 64 * wr;
             jp = 128 + 64 * wc;
             r0 = I0 + 64 * wr;
             c0 = J0 + 64 * wc;
+            kind = 0;
         } else if (wave < 2) {
             ip = jp = 64 * wave;
             r0 = c0 = I0 + 64 * wave;
+            kind = 1;
         } else {
             ip = 64;
-            jp = 0;
+            jp = 32 * (wave - 2);
             r0 = I0 + 64;
-            c0 = I0;
-            write = wave == 2;
+            c0 = I0 + jp;
+            kind = 2;
         }
     };
 
@@ -485,9 +499,8 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
         const WgSub &sb = a.subs[w.cs >> 24];
         r_tcount = sb.t_count;
         r_nstage = (sb.t_count + TKS - 1) / TKS;
-        int ip, jp, r0, c0;
-        bool write;
-        role(w, ip, jp, r0, c0, write);
+        int ip, jp, r0, c0, kind;
+        role(w, ip, jp, r0, c0, kind);
 #pragma unroll
         for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
@@ -566,9 +579,8 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
         const WgSub &sb = a.subs[w.cs >> 24];
         const int f = (int)(w.cs & 0xFFFFFFu);
         const int nst = (sb.t_count + TKS - 1) / TKS;
-        int ip, jp, r0, c0;
-        bool write;
-        role(w, ip, jp, r0, c0, write);
+        int ip, jp, r0, c0, kind;
+        role(w, ip, jp, r0, c0, kind);
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -577,52 +589,58 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
                 accI[x][y] = AccT{};
             }
         int32_t S[2] = {0, 0}; // this lane's part of S_i of rows l % 32 of I blocks 0, 1 (FUSE)
-        // the stage's fragments were read by the previous step (RA); unpack
-        // and multiply, then publish and read the next stage
-        // The stage's fragments were read by the previous step (RA). Once
-        // its last K step is unpacked RA is free, so the next stage is
-        // published and read into RA between the first wg_split() blocks of
-        // that K step's MFMAs and the rest: the MFMAs before the barrier
-        // cover its wait, those after cover the reads' latency.
-        for (int k = 0; k < nst; ++k, ++s) {
-            if (issued < n_total) d_issue();
-            const bool more = s + 1 < n_total;
-            // wave 3 of a diagonal tile has no quarter of its own: it keeps
-            // copying and synchronising but leaves its SIMD's matrix core to
-            // the other workgroup (uniform branches outside the MFMA chains)
-            if constexpr (ENG == ENG_F8) {
-                if (write) wg_f8_stage(RA, accR, accI);
-                if (more) {
-                    prep_stage(s + 1);
-                    read_frags((s + 1) % WG_NBUF, RA);
-                }
-            } else {
-                if (write) {
-                    if constexpr (IN_BITS == 4) {
-                        wg_unpack<FUSE>(RA, 0, O0, S);
-                        wg_mfma(O0, accR, accI);
-                        wg_unpack<FUSE>(RA, 1, O0, S);
-                    } else {
-                        wg8_unpack<FUSE>(RA, O0, S);
+        // The stage loop of one role kind (MASK: its blocks). The stage's
+        // fragments were read by the previous step (RA). Once its last K step
+        // is unpacked RA is free, so the next stage is published and read into
+        // RA between the first wg_split() blocks of that K step's MFMAs and
+        // the rest: the MFMAs before the barrier cover its wait, those after
+        // cover the reads' latency. A diagonal quarter sums no S_i: its own
+        // diagonal holds them.
+        auto stages = [&](auto mask_c) {
+            constexpr int MASK = decltype(mask_c)::value;
+            constexpr int NY = (MASK & 0xC) ? 2 : 1;
+            constexpr bool SUMS = FUSE && MASK != 0xB;
+            for (int k = 0; k < nst; ++k, ++s) {
+                if (issued < n_total) d_issue();
+                const bool more = s + 1 < n_total;
+                if constexpr (ENG == ENG_F8) {
+                    wg_f8_stage<MASK>(RA, accR, accI);
+                    if (more) {
+                        prep_stage(s + 1);
+                        read_frags((s + 1) % WG_NBUF, RA);
                     }
-                    wg_mfma_blocks<0, wg_split<IN_BITS>()>(O0, accR, accI);
+                } else {
+                    if constexpr (IN_BITS == 4) {
+                        wg_unpack<SUMS, NY>(RA, 0, O0, S);
+                        wg_mfma<MASK>(O0, accR, accI);
+                        wg_unpack<SUMS, NY>(RA, 1, O0, S);
+                    } else {
+                        wg8_unpack<SUMS, NY>(RA, O0, S);
+                    }
+                    wg_mfma_blocks<0, wg_split<IN_BITS>(), MASK>(O0, accR, accI);
+                    if (more) {
+                        prep_stage(s + 1);
+                        read_frags((s + 1) % WG_NBUF, RA);
+                    }
+                    wg_mfma_blocks<wg_split<IN_BITS>(), 4, MASK>(O0, accR, accI);
                 }
-                if (more) {
-                    prep_stage(s + 1);
-                    read_frags((s + 1) % WG_NBUF, RA);
-                }
-                if (write) wg_mfma_blocks<wg_split<IN_BITS>(), 4>(O0, accR, accI);
+                if (more) r_advance();
             }
-            if (more) r_advance();
-        }
+        };
+        if (kind == 0) stages(std::integral_constant<int, 0xF>{});
+        else if (kind == 1) stages(std::integral_constant<int, 0xB>{});
+        else stages(std::integral_constant<int, 0x3>{});
 
         // ---- flush. 32 x 32 MFMA result: lane l holds column l % 32 of rows
         // 8 (r / 4) + 4 (l / 32) + r % 4. Buffer loads / stores relative to
-        // row r0: elements above the diagonal, past N, or of a wave that
-        // writes nothing get an out-of-range offset (loads read 0, stores are
+        // row r0: elements above the diagonal, past N, or in a block the wave
+        // does not own get an out-of-range offset (loads read 0, stores are
         // dropped), no branches. S: lanes l and l + 32 hold halves of the row
-        // sum of row l % 32 of I block x; the int8 engines add it to Im.
+        // sum of row l % 32 of I block x; the int8 engines add it to Im. A
+        // diagonal quarter takes S_i from its own diagonal cell instead (Im V_ii
+        // = 0, so the raw diagonal word is -S_i).
         const int N = sb.n_inputs;
+        const int ny = kind == 2 ? 1 : 2; // J blocks the wave owns
         // lane-derived flush offsets from an opaque copy of the lane index, so
         // that they are not hoisted out of the tile loop (and kept live in
         // registers across the stage loop)
@@ -669,10 +687,12 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
                     const int i = r0 + 32 * x + rr;
                     const int rel = (int)((int64_t)i * (i + 1) / 2 - rb0);
                     sv[e] = FUSE ? __shfl(S[x], rr) : 0;
+                    if (FUSE && ENG == ENG_I8 && kind == 1)
+                        sv[e] -= (int32_t)acc_word<IN_BITS>(__shfl(accI[x][x][4 * q + e], rr + 32 * lh));
 #pragma unroll
                     for (int y = 0; y < 2; ++y) {
                         const int j = c0 + 32 * y + lc;
-                        off[e][y] = (write && i < N && j <= i) ? (uint32_t)(rel + j) * 8u : OOR;
+                        off[e][y] = (y < ny && i < N && j <= i) ? (uint32_t)(rel + j) * 8u : OOR;
                     }
                 }
                 u32x2 old[4][2];

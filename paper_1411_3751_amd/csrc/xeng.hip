@@ -276,9 +276,10 @@ void build_schedule(WavePlan &p, const std::vector<Sub> &subs, int n_cu, int wg_
                     It it;
                     it.w.cs = (uint32_t)f | ((uint32_t)k << 24);
                     it.w.ij = (uint32_t)bi | ((uint32_t)bj << 16);
-                    // every tile takes one stage loop per stage (a diagonal
-                    // tile keeps all 4 waves busy too), plus a per-tile flush
-                    it.cost = per_stage + 2.0;
+                    // a stage loop per stage (the busiest wave of a diagonal
+                    // tile has 3 MFMA tiles, off the diagonal 4), plus a
+                    // per-tile flush
+                    it.cost = per_stage * (bi == bj ? 0.75 : 1.0) + 2.0;
                     all.push_back(it);
                 }
     }
