@@ -254,53 +254,37 @@ __device__ __forceinline__ void wg_mfma(const WgOps &o, i32x16 (&accR)[2][2], i3
 
 // ---- FP8 engine (OCP e4m3 operands, fp32 accumulation) -----------------
 //
-// Every 4-bit value v in [-8, 7] and every product of two of them is exact
-// in e4m3 / fp32. A nibble becomes its e4m3 code by a 16-entry table lookup
-// done as two v_perm_b32 byte lookups (v >= 0 and v < 0 halves, indexed by
-// the nibble's low 3 bits) merged under a per-byte sign mask. The mask comes
-// from v_perm_b32's sign-replicating selectors 8..11, which copy bit 7 of
-// bytes 1, 3, 5, 7 of the 8-byte source {S0 : S1}: with S1 = w << 8 and
-// S0 = w those are bytes 0, 2, 1, 3 of w.
-//
-// The operands need no ~im trick here (e4m3 holds +8), so the float
-// accumulators hold Re V and Im V themselves; a segment of at most SEG_T
-// samples keeps every partial sum at most 128 * 2^15 = 2^22 < 2^24, where
-// fp32 is exact, and the flush converts them to int32 exactly.
+// Operands are offset values u = v + 8 in 0..15 (the nibble with its sign
+// bit flipped: two bit operations per 4 samples). The e4m3 code whose bit
+// pattern is u stands for u * 2^-9 exactly (0..7 are the subnormals m * 2^-9,
+// 8..15 the first normal binade (1 + m/8) * 2^-6), so with block scales of
+// 2^9 on both operands every product is the exact integer u_a u_b; the sign
+// bit negates a code exactly. Per K step and 32 x 32 block:
+//   accR += u(re_I) u(re_J) + u(im_I) u(im_J),
+//   accI += u(im_I) u(re_J) - u(re_I) u(im_J),
+// so that, with P_n = sum_t u(re_n), Q_n = sum_t u(im_n) over the launch's
+// rows (T' of them, the zero rows that pad a segment to whole stages
+// included: for them every u is 8 and every difference below is 0),
+//   Re V_ij = accR - 8 (P_i + Q_i + P_j + Q_j) + 128 T',
+//   Im V_ij = accI - 8 (Q_i - P_i) + 8 (Q_j - P_j).
+// Each wave sums P and Q of its own I rows and J columns (byte-wise adds of
+// the 8 code words of a fragment, at most 8 * 15 per byte, then one
+// v_sad_u8); the flush applies the correction, so the accumulator holds the
+// exact sums, as the raw convention allows. The fp32 sums stay exact: a
+// segment of at most SEG_T = 2^15 samples keeps |accR| <= 2^15 * 450 < 2^24.
 constexpr int ENG_I8 = 0;
 constexpr int ENG_F8 = 1;
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef int32_t i32x8 __attribute__((ext_vector_type(8)));
 
-// e4m3 codes of k and of k - 8 for k = 0..7 (bytes 0..3 in the S1 word,
-// 4..7 in the S0 word)
-constexpr uint32_t F8_POS_LO = 0x44403800u; // 0, 1, 2, 3
-constexpr uint32_t F8_POS_HI = 0x4E4C4A48u; // 4, 5, 6, 7
-constexpr uint32_t F8_NEG_LO = 0xCACCCED0u; // -8, -7, -6, -5
-constexpr uint32_t F8_NEG_HI = 0xB8C0C4C8u; // -4, -3, -2, -1
-constexpr uint32_t F8_SIGNSEL = 0x0B090A08u; // bit 7 of bytes 0, 1, 2, 3 of w
+constexpr int F8_SCALE = 127 + 9; // E8M0 block scale 2^9 on each operand
 
-// idx: low 3 bits of 4 nibbles (one per byte); neg: 0xFF in the bytes whose
-// nibble is negative
-__device__ __forceinline__ uint32_t f8_lookup(uint32_t idx, uint32_t neg)
-{
-    const uint32_t p = __builtin_amdgcn_perm(F8_POS_HI, F8_POS_LO, idx);
-    const uint32_t n = __builtin_amdgcn_perm(F8_NEG_HI, F8_NEG_LO, idx);
-    return (n & neg) | (p & ~neg);
-}
+// offset codes of the real parts (high nibbles) of 4 packed samples
+__device__ __forceinline__ uint32_t f8_re(uint32_t w) { return ((w >> 4) & 0x0F0F0F0Fu) ^ 0x08080808u; }
 
-// e4m3 codes of the real parts (high nibbles) of 4 packed samples
-__device__ __forceinline__ uint32_t f8_re(uint32_t w)
-{
-    return f8_lookup((w >> 4) & 0x07070707u, __builtin_amdgcn_perm(w, w << 8, F8_SIGNSEL));
-}
-
-// e4m3 codes of the imaginary parts (low nibbles) of 4 packed samples
-__device__ __forceinline__ uint32_t f8_im(uint32_t w)
-{
-    const uint32_t w4 = w << 4;
-    return f8_lookup(w & 0x07070707u, __builtin_amdgcn_perm(w4, w4 << 8, F8_SIGNSEL));
-}
+// offset codes of the imaginary parts (low nibbles) of 4 packed samples
+__device__ __forceinline__ uint32_t f8_im(uint32_t w) { return (w & 0x0F0F0F0Fu) ^ 0x08080808u; }
 
 // raw dword d (0..7) of side sd, block blk of a stage: K steps 0 and 1 of
 // the int8 layout concatenated (A and B lanes hold the same samples at the
@@ -311,22 +295,39 @@ __device__ __forceinline__ uint32_t wg_raw_dw(const WgRaw &R, int sd, int blk, i
     return (uint32_t)((d & 1) ? v.y : v.x);
 }
 
-// One stage (64 samples) of the FP8 engine: 16 v_mfma_scale_f32_32x32x64_f8f6f4
-// (scales 2^0) over 2 x 2 tiles of 32 x 32:
-//   accR += re_I re_J + im_I im_J,  accI += im_I re_J + re_I (-im_J).
+// this lane's part of the sum of the 32 codes of a fragment (8 words)
+__device__ __forceinline__ int32_t f8_sum(const i32x8 &c, int32_t acc)
+{
+    const uint32_t b = (uint32_t)c[0] + (uint32_t)c[1] + (uint32_t)c[2] + (uint32_t)c[3] + (uint32_t)c[4] +
+                       (uint32_t)c[5] + (uint32_t)c[6] + (uint32_t)c[7];
+    return (int32_t)__builtin_amdgcn_sad_u8(b, 0u, (uint32_t)acc);
+}
+
+// Code sums of a wave's fragments: P (real) and Q (imaginary) of I blocks x
+// and of J blocks y, this lane's half of row / column l % 32.
+struct F8Sums {
+    int32_t pi[2], qi[2], pj[2], qj[2];
+};
+
+// One stage (64 samples) of the FP8 engine on the 2 x 2 tiles of 32 x 32
+// that MASK names: v_mfma_scale_f32_32x32x64_f8f6f4 with scales 2^9, and the
+// code sums of the fragments used.
 template <int MASK>
-__device__ __forceinline__ void wg_f8_stage(const WgRaw &R, f32x16 (&accR)[2][2],
-                                            f32x16 (&accI)[2][2])
+__device__ __forceinline__ void wg_f8_stage(const WgRaw &R, f32x16 (&accR)[2][2], f32x16 (&accI)[2][2],
+                                            F8Sums &sm)
 {
     i32x8 reI[2], imI[2];
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < 2; ++x) {
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             const uint32_t w = wg_raw_dw(R, 0, x, d);
             reI[x][d] = (int32_t)f8_re(w);
             imI[x][d] = (int32_t)f8_im(w);
         }
+        sm.pi[x] = f8_sum(reI[x], sm.pi[x]);
+        sm.qi[x] = f8_sum(imI[x], sm.qi[x]);
+    }
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
         if (!((MASK >> (2 * y)) & 3)) continue; // no block of this J column
@@ -339,22 +340,24 @@ __device__ __forceinline__ void wg_f8_stage(const WgRaw &R, f32x16 (&accR)[2][2]
             reJ[d] = (int32_t)f8_re(w);
             imJ[d] = (int32_t)f8_im(w);
         }
+        sm.pj[y] = f8_sum(reJ, sm.pj[y]);
+        sm.qj[y] = f8_sum(imJ, sm.qj[y]);
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
             if (!((MASK >> (x + 2 * y)) & 1)) continue;
-            accR[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(reI[x], reJ, accR[x][y],
-                                                                         0, 0, 0, 127, 0, 127);
-            accI[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(imI[x], reJ, accI[x][y],
-                                                                         0, 0, 0, 127, 0, 127);
-            accR[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(imI[x], imJ, accR[x][y],
-                                                                         0, 0, 0, 127, 0, 127);
+            accR[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(reI[x], reJ, accR[x][y], 0, 0, 0,
+                                                                         F8_SCALE, 0, F8_SCALE);
+            accI[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(imI[x], reJ, accI[x][y], 0, 0, 0,
+                                                                         F8_SCALE, 0, F8_SCALE);
+            accR[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(imI[x], imJ, accR[x][y], 0, 0, 0,
+                                                                         F8_SCALE, 0, F8_SCALE);
         }
         const i32x8 niJ = imJ ^ (int32_t)0x80808080u;
 #pragma unroll
         for (int x = 0; x < 2; ++x)
             if ((MASK >> (x + 2 * y)) & 1)
-                accI[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(reI[x], niJ, accI[x][y],
-                                                                             0, 0, 0, 127, 0, 127);
+                accI[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(reI[x], niJ, accI[x][y], 0, 0,
+                                                                             0, F8_SCALE, 0, F8_SCALE);
     }
 }
 
@@ -589,6 +592,7 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
                 accI[x][y] = AccT{};
             }
         int32_t S[2] = {0, 0}; // this lane's part of S_i of rows l % 32 of I blocks 0, 1 (FUSE)
+        F8Sums sm = {};        // FP8 engine: code sums of the fragments
         // The stage loop of one role kind (MASK: its blocks). The stage's
         // fragments were read by the previous step (RA). Once its last K step
         // is unpacked RA is free, so the next stage is published and read into
@@ -604,7 +608,11 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
                 if (issued < n_total) d_issue();
                 const bool more = s + 1 < n_total;
                 if constexpr (ENG == ENG_F8) {
-                    wg_f8_stage<MASK>(RA, accR, accI);
+                    wg_f8_stage<MASK>(RA, accR, accI, sm);
+                    // the next stage's reads stay behind this stage's MFMAs
+                    // (hoisted above them they would hold RA live beside the
+                    // codes)
+                    __builtin_amdgcn_sched_barrier(0);
                     if (more) {
                         prep_stage(s + 1);
                         read_frags((s + 1) % WG_NBUF, RA);
@@ -627,9 +635,16 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
                 if (more) r_advance();
             }
         };
-        if (kind == 0) stages(std::integral_constant<int, 0xF>{});
-        else if (kind == 1) stages(std::integral_constant<int, 0xB>{});
-        else stages(std::integral_constant<int, 0x3>{});
+        if constexpr (ENG == ENG_F8) {
+            // one stage loop for every role (a role's blocks outside its mask
+            // are computed but never written): a single copy of the FP8 loop
+            // leaves its register allocation room
+            stages(std::integral_constant<int, 0xF>{});
+        } else {
+            if (kind == 0) stages(std::integral_constant<int, 0xF>{});
+            else if (kind == 1) stages(std::integral_constant<int, 0xB>{});
+            else stages(std::integral_constant<int, 0x3>{});
+        }
 
         // ---- flush. 32 x 32 MFMA result: lane l holds column l % 32 of rows
         // 8 (r / 4) + 4 (l / 32) + r % 4. Buffer loads / stores relative to
@@ -672,6 +687,26 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
                 S[x] -= (int32_t)dg.y;
             }
         }
+        // FP8 engine: the offset correction, per row (lanes l and l + 32 hold
+        // halves of row l % 32's sums; the row's value is fetched by its
+        // lanes) and per column (this lane's own column l % 32)
+        int32_t fr[2] = {0, 0}, fi[2] = {0, 0}, gr[2] = {0, 0}, gi[2] = {0, 0};
+        if constexpr (ENG == ENG_F8) {
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                const int32_t p = sm.pi[x] + __shfl_xor(sm.pi[x], 32);
+                const int32_t q = sm.qi[x] + __shfl_xor(sm.qi[x], 32);
+                fr[x] = 128 * TKS * nst - 8 * (p + q); // row part of the Re correction
+                fi[x] = -8 * (q - p);                  // row part of the Im correction
+            }
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                const int32_t p = sm.pj[y] + __shfl_xor(sm.pj[y], 32);
+                const int32_t q = sm.qj[y] + __shfl_xor(sm.qj[y], 32);
+                gr[y] = -8 * (p + q);
+                gi[y] = 8 * (q - p);
+            }
+        }
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -680,13 +715,15 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
                 // hoisting every group's loads and offsets)
                 __builtin_amdgcn_sched_barrier(0);
                 uint32_t off[4][2];
-                int32_t sv[4];
+                int32_t sv[4], cr[4], ci[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int rr = 8 * q + 4 * lh + e;
                     const int i = r0 + 32 * x + rr;
                     const int rel = (int)((int64_t)i * (i + 1) / 2 - rb0);
                     sv[e] = FUSE ? __shfl(S[x], rr) : 0;
+                    cr[e] = ENG == ENG_F8 ? __shfl(fr[x], rr) : 0;
+                    ci[e] = ENG == ENG_F8 ? __shfl(fi[x], rr) : 0;
                     if (FUSE && ENG == ENG_I8 && kind == 1)
                         sv[e] -= (int32_t)acc_word<IN_BITS>(__shfl(accI[x][x][4 * q + e], rr + 32 * lh));
 #pragma unroll
@@ -706,9 +743,10 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
                 for (int e = 0; e < 4; ++e)
 #pragma unroll
                     for (int y = 0; y < 2; ++y) {
-                        const u32x2 v = {old[e][y].x + acc_word<IN_BITS>(accR[x][y][4 * q + e]),
+                        const u32x2 v = {old[e][y].x + acc_word<IN_BITS>(accR[x][y][4 * q + e]) +
+                                             (uint32_t)(cr[e] + gr[y]),
                                          old[e][y].y + acc_word<IN_BITS>(accI[x][y][4 * q + e]) +
-                                             (uint32_t)sv[e]};
+                                             (uint32_t)(sv[e] + ci[e] + gi[y])};
                         __builtin_amdgcn_raw_buffer_store_b64(v, drs, (int)off[e][y], 0, 0);
                     }
             }
