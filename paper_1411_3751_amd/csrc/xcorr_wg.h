@@ -303,10 +303,12 @@ __device__ __forceinline__ int32_t f8_sum(const i32x8 &c, int32_t acc)
     return (int32_t)__builtin_amdgcn_sad_u8(b, 0u, (uint32_t)acc);
 }
 
-// Code sums of a wave's fragments: P (real) and Q (imaginary) of I blocks x
-// and of J blocks y, this lane's half of row / column l % 32.
+// Code sums of the two fragments a wave sums: P (real) and Q (imaginary) of
+// I block sx (a) and J block sy (b), this lane's half of row / column l % 32.
+// Each input of a tile is summed by one wave only, and the flush shares the
+// sums through LDS.
 struct F8Sums {
-    int32_t pi[2], qi[2], pj[2], qj[2];
+    int32_t pa, qa, pb, qb;
 };
 
 // One stage (64 samples) of the FP8 engine on the 2 x 2 tiles of 32 x 32
@@ -314,7 +316,7 @@ struct F8Sums {
 // code sums of the fragments used.
 template <int MASK>
 __device__ __forceinline__ void wg_f8_stage(const WgRaw &R, f32x16 (&accR)[2][2], f32x16 (&accI)[2][2],
-                                            F8Sums &sm)
+                                            F8Sums &sm, int sx, int sy)
 {
     i32x8 reI[2], imI[2];
 #pragma unroll
@@ -325,8 +327,10 @@ __device__ __forceinline__ void wg_f8_stage(const WgRaw &R, f32x16 (&accR)[2][2]
             reI[x][d] = (int32_t)f8_re(w);
             imI[x][d] = (int32_t)f8_im(w);
         }
-        sm.pi[x] = f8_sum(reI[x], sm.pi[x]);
-        sm.qi[x] = f8_sum(imI[x], sm.qi[x]);
+        if (sx == x) {
+            sm.pa = f8_sum(reI[x], sm.pa);
+            sm.qa = f8_sum(imI[x], sm.qa);
+        }
     }
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
@@ -340,8 +344,10 @@ __device__ __forceinline__ void wg_f8_stage(const WgRaw &R, f32x16 (&accR)[2][2]
             reJ[d] = (int32_t)f8_re(w);
             imJ[d] = (int32_t)f8_im(w);
         }
-        sm.pj[y] = f8_sum(reJ, sm.pj[y]);
-        sm.qj[y] = f8_sum(imJ, sm.qj[y]);
+        if (sy == y) {
+            sm.pb = f8_sum(reJ, sm.pb);
+            sm.qb = f8_sum(imJ, sm.qb);
+        }
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
             if (!((MASK >> (x + 2 * y)) & 1)) continue;
@@ -378,6 +384,8 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
     static_assert(Geo::TKS * Geo::ROWB == WG_STAGE, "stage size");
     typedef typename std::conditional<ENG == ENG_F8, f32x16, i32x16>::type AccT;
     __shared__ __attribute__((aligned(16))) uint8_t lds[WG_NBUF * WG_STAGE];
+    // FP8 engine: code sums of a tile's inputs by staged-row position, P then Q
+    __shared__ int32_t f8t[ENG == ENG_F8 ? 2 * 256 : 1];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -593,6 +601,11 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
             }
         int32_t S[2] = {0, 0}; // this lane's part of S_i of rows l % 32 of I blocks 0, 1 (FUSE)
         F8Sums sm = {};        // FP8 engine: code sums of the fragments
+        // which fragments this wave sums: off the diagonal I block (wave & 1)
+        // and J block (wave >> 1); on it (J = I) waves 0 and 1 sum inputs
+        // 0..63 and 64..127 (their I block 0 and J block 1), waves 2, 3 none
+        const int sx = kind == 0 ? (wave & 1) : (wave < 2 ? 0 : -1);
+        const int sy = kind == 0 ? (wave >> 1) : (wave < 2 ? 1 : -1);
         // The stage loop of one role kind (MASK: its blocks). The stage's
         // fragments were read by the previous step (RA). Once its last K step
         // is unpacked RA is free, so the next stage is published and read into
@@ -608,7 +621,7 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
                 if (issued < n_total) d_issue();
                 const bool more = s + 1 < n_total;
                 if constexpr (ENG == ENG_F8) {
-                    wg_f8_stage<MASK>(RA, accR, accI, sm);
+                    wg_f8_stage<MASK>(RA, accR, accI, sm, sx, sy);
                     // the next stage's reads stay behind this stage's MFMAs
                     // (hoisted above them they would hold RA live beside the
                     // codes)
@@ -692,17 +705,30 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
         // lanes) and per column (this lane's own column l % 32)
         int32_t fr[2] = {0, 0}, fi[2] = {0, 0}, gr[2] = {0, 0}, gi[2] = {0, 0};
         if constexpr (ENG == ENG_F8) {
+            // this wave's sums into the table (full sums: both halves), then
+            // every wave's rows and columns out of it
+            const int32_t pa = sm.pa + __shfl_xor(sm.pa, 32), qa = sm.qa + __shfl_xor(sm.qa, 32);
+            const int32_t pb = sm.pb + __shfl_xor(sm.pb, 32), qb = sm.qb + __shfl_xor(sm.qb, 32);
+            // (every wave is done reading the previous tile's table)
+            asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+            if (lh == 0 && sx >= 0) {
+                f8t[ip + 32 * sx + lc] = pa;
+                f8t[256 + ip + 32 * sx + lc] = qa;
+            }
+            if (lh == 0 && sy >= 0) {
+                f8t[jp + 32 * sy + lc] = pb;
+                f8t[256 + jp + 32 * sy + lc] = qb;
+            }
+            asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 #pragma unroll
             for (int x = 0; x < 2; ++x) {
-                const int32_t p = sm.pi[x] + __shfl_xor(sm.pi[x], 32);
-                const int32_t q = sm.qi[x] + __shfl_xor(sm.qi[x], 32);
+                const int32_t p = f8t[ip + 32 * x + lc], q = f8t[256 + ip + 32 * x + lc];
                 fr[x] = 128 * TKS * nst - 8 * (p + q); // row part of the Re correction
                 fi[x] = -8 * (q - p);                  // row part of the Im correction
             }
 #pragma unroll
             for (int y = 0; y < 2; ++y) {
-                const int32_t p = sm.pj[y] + __shfl_xor(sm.pj[y], 32);
-                const int32_t q = sm.qj[y] + __shfl_xor(sm.qj[y], 32);
+                const int32_t p = f8t[jp + 32 * y + lc], q = f8t[256 + jp + 32 * y + lc];
                 gr[y] = -8 * (p + q);
                 gi[y] = 8 * (q - p);
             }
