@@ -68,7 +68,7 @@ extern "C" {
 
 #define XENG_MAX_DUMP_SAMPLES_4BIT 16777215LL /* floor((2^31 - 1) / 128) */
 #define XENG_MAX_DUMP_SAMPLES_8BIT 65535LL    /* floor((2^31 - 1) / 32768) */
-#define XENG_MAX_CALL_SAMPLES_FP8 32768LL     /* samples per fp32 partial sum: 128 * 2^15 < 2^24 */
+#define XENG_MAX_CALL_SAMPLES_FP8 32768LL     /* samples per fp32 partial sum: 450 * 2^15 < 2^24 */
 
 typedef struct xeng_ctx xeng_ctx; /* opaque, library-owned */
 

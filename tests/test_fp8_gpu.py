@@ -58,7 +58,9 @@ def test_fp8_parity_random(torch_cuda, oracle_lib, N, F, T):
 @pytest.mark.parametrize("code", [0x88, 0x77, 0x8F, 0xF8, 0x18])
 def test_fp8_extremes_two_segments(torch_cuda, oracle_lib, code):
     # every sample at an extreme code for 40000 samples: one full 32768-sample
-    # fp32 segment at the largest magnitudes (128 * 32768 = 2^22) plus a tail
+    # fp32 segment at the largest magnitudes plus a tail (with the engine's
+    # offset operands u = v + 8, code 0x77 gives 450 per sample in the Re
+    # partial sums: 450 * 32768 < 2^24)
     print("case fp8 extremes code=%#x" % code, flush=True)
     s = np.full((40000, 1, 32), code, np.uint8)
     want = oracle_lib.narrow(oracle_lib.correlate(s, 4))
