@@ -554,10 +554,23 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
             if (++r_item < it_end) r_setup(r_item);
         }
     };
-    auto read_frags = [&](int slot, WgRaw &R) {
+    // K steps [K0, K1) of a stage's fragments into R, at the offsets fo
+    // (the read cursor's stage) or, for the second K step of the stage being
+    // multiplied, fo_mul: the offsets of that stage's role, kept when its
+    // first K step was read (the cursor has moved on, possibly to a tile of
+    // another role)
+    int fo_mul[2][2];
+    auto read_frags_k = [&](int slot, WgRaw &R, auto k0_c, auto k1_c) {
+        constexpr int K0 = decltype(k0_c)::value, K1 = decltype(k1_c)::value;
         const uint8_t *b = lds + slot * WG_STAGE;
+        if constexpr (K0 == 0) {
 #pragma unroll
-        for (int k = 0; k < 2; ++k)
+            for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+                for (int blk = 0; blk < 2; ++blk) fo_mul[sd][blk] = fo[sd][blk];
+        }
+#pragma unroll
+        for (int k = K0; k < K1; ++k)
 #pragma unroll
             for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
@@ -567,21 +580,32 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
                         if constexpr (IN_BITS == 4) {
                             // K step k, rows 8 i apart
                             R[k][sd][blk][i] = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
-                                (lds_i32x2 *)(b + fo[sd][blk] + (32 * k + 8 * i) * Geo::ROWB));
+                                (lds_i32x2 *)(b + fo_mul[sd][blk] + (32 * k + 8 * i) * Geo::ROWB));
                         } else {
                             // load 2 k + i, rows 4 (2 k + i) apart
                             R[k][sd][blk][i] = (i32x2)__builtin_amdgcn_ds_read_tr16_b64_v4i16(
-                                (lds_i16x4 *)(b + fo[sd][blk] + 4 * (2 * k + i) * Geo::ROWB));
+                                (lds_i16x4 *)(b + fo_mul[sd][blk] + 4 * (2 * k + i) * Geo::ROWB));
                         }
                     }
     };
+    auto read_frags = [&](int slot, WgRaw &R) {
+        read_frags_k(slot, R, std::integral_constant<int, 0>{}, std::integral_constant<int, 2>{});
+    };
+    // 4-bit input on the int8 engine reads a stage's second K step only when
+    // the stage is multiplied (the first right after the barrier that
+    // publishes it): two bursts of 8 reads instead of one of 16, the second
+    // covered by the first K step's MFMAs
+    constexpr bool SPLIT_READS = ENG == ENG_I8 && IN_BITS == 4;
 
     AccT accR[2][2], accI[2][2];
     WgRaw RA;
     WgOps O0;
     r_setup(it_begin);
     prep_stage(0);
-    read_frags(0, RA);
+    if constexpr (SPLIT_READS)
+        read_frags_k(0, RA, std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{});
+    else
+        read_frags(0, RA);
     r_advance();
     int s = 0; // global index of the stage being multiplied
 
@@ -631,6 +655,9 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
                         read_frags((s + 1) % WG_NBUF, RA);
                     }
                 } else {
+                    if constexpr (SPLIT_READS)
+                        read_frags_k(s % WG_NBUF, RA, std::integral_constant<int, 1>{},
+                                     std::integral_constant<int, 2>{});
                     if constexpr (IN_BITS == 4) {
                         wg_unpack<SUMS, NY>(RA, 0, O0, S);
                         wg_mfma<MASK>(O0, accR, accI);
@@ -641,7 +668,11 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
                     wg_mfma_blocks<0, wg_split<IN_BITS>(), MASK>(O0, accR, accI);
                     if (more) {
                         prep_stage(s + 1);
-                        read_frags((s + 1) % WG_NBUF, RA);
+                        if constexpr (SPLIT_READS)
+                            read_frags_k((s + 1) % WG_NBUF, RA, std::integral_constant<int, 0>{},
+                                         std::integral_constant<int, 1>{});
+                        else
+                            read_frags((s + 1) % WG_NBUF, RA);
                     }
                     wg_mfma_blocks<wg_split<IN_BITS>(), 4, MASK>(O0, accR, accI);
                 }
