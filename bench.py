@@ -37,14 +37,40 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1411_3751_amd", "csrc", f)
 SN_SOURCES = ["xcorr_sn.h", "xcorr_wg.h", "xcorr_i8.h"]  # the small-N kernel and its helpers
 
 
+def code_text(text: str) -> str:
+    """C++ source without its comments and with whitespace runs collapsed:
+    what the compiler sees, so that a comment edit keeps a summary valid."""
+    import re
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c == '"' or c == "'":  # string or character literal, kept whole
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return re.sub(r"\s+", " ", "".join(out)).strip()
+
+
 def kernel_source_hash(files=None) -> str:
     import hashlib
     h = hashlib.sha256()
     srcs = KERNEL_SOURCES if files is None else [
         os.path.join(ROOT, "paper_1411_3751_amd", "csrc", f) for f in files]
     for f in srcs:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

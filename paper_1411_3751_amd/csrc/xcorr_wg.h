@@ -116,10 +116,10 @@ struct WgArgs {
 };
 
 // Wait until at most 4 * n of this wave's copies are outstanding and every
-// LDS read it issued has returned, then barrier. The LDS wait matters for a
-// wave that read a stage's fragments without consuming them (wave 3 of a
-// diagonal tile): past the barrier another wave may copy a later stage into
-// the slot those reads came from.
+// LDS read it issued has returned, then barrier. The LDS wait keeps a slot's
+// reads ahead of the copies into it: past the barrier another wave may copy
+// a later stage into the slot a read of this wave came from, whether or not
+// that read's data has been used yet.
 __device__ __forceinline__ void wg_wait_barrier(int n)
 {
     switch (n) {
