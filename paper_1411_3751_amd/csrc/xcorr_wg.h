@@ -24,9 +24,13 @@
 //
 // Each wave computes a 64 x 64 quarter of the tile as 2 x 2 MFMA tiles of
 // 32 x 32. On a diagonal tile (J = I, only the I half is copied) the lower
-// triangle is 10 such tiles: waves 0, 1 take the diagonal quarters less
-// their upper tile (3 each), waves 2, 3 the two 64 x 32 columns below the
-// first quarter (2 each).
+// triangle is 10 such tiles. With 4-bit input on the int8 engine they are
+// dealt as 20 half tiles (a half being one of the two K steps of every
+// stage), 5 per wave: each wave multiplies two whole tiles and one half of
+// a tile whose other half another wave multiplies, and the two halves are
+// added through LDS at the flush. Otherwise waves 0, 1 take the diagonal
+// quarters less their upper tile (3 each), waves 2, 3 the two 64 x 32
+// columns below the first quarter (2 each).
 //
 // Operands: re, im and ~im (= -im - 1, so that -(-8) or -(-128) never has to
 // fit in int8); 4-bit values are scaled by 16 by the nibble masks (see
@@ -148,14 +152,15 @@ __device__ __forceinline__ u32x4 wg_raw(const WgRaw &R, int k, int sd, int blk)
 }
 
 // ... and S[x] += the real parts of its I-side words (row sums for the Im
-// correction): 4 v_dot8_i32_i4 with weights 1 on the real nibbles. NY: the
-// J blocks the wave multiplies (2, or 1 for the column roles of a diagonal
-// tile).
-template <bool SUMS, int NY>
+// correction): 4 v_dot8_i32_i4 with weights 1 on the real nibbles. IM, JM:
+// the I and J blocks (bit x, bit y) that the K step's MFMAs use.
+template <bool SUMS, int IM, int JM>
 __device__ __forceinline__ void wg_unpack(const WgRaw &R, int k, WgOps &o, int32_t (&S)[2])
 {
+    static_assert(!SUMS || IM == 3, "row sums need every I block");
 #pragma unroll
     for (int x = 0; x < 2; ++x) {
+        if (!((IM >> x) & 1)) continue;
         const u32x4 p = wg_raw(R, k, 0, x);
         o.reI[x] = (i32x4)(p & 0xF0F0F0F0u);
         o.imI[x] = (i32x4)((p << 4) & 0xF0F0F0F0u);
@@ -165,7 +170,8 @@ __device__ __forceinline__ void wg_unpack(const WgRaw &R, int k, WgOps &o, int32
         }
     }
 #pragma unroll
-    for (int y = 0; y < NY; ++y) {
+    for (int y = 0; y < 2; ++y) {
+        if (!((JM >> y) & 1)) continue;
         const u32x4 p = wg_raw(R, k, 1, y);
         const u32x4 im = (p << 4) & 0xF0F0F0F0u;
         o.reJ[y] = (i32x4)(p & 0xF0F0F0F0u);
@@ -233,6 +239,10 @@ __device__ __forceinline__ void wg_mfma_blocks(const WgOps &o, i32x16 (&accR)[2]
 // latency; the ones before cover the barrier's wait). Measured best: half
 // for 4-bit input (two K steps per stage), one block for 8-bit (one K step).
 template <int IN_BITS> constexpr int wg_split() { return IN_BITS == 4 ? 2 : 1; }
+
+// The I blocks (bit x) and J blocks (bit y) that the blocks of MASK use.
+constexpr int wg_imask(int m) { return ((m & 5) ? 1 : 0) | ((m & 10) ? 2 : 0); }
+constexpr int wg_jmask(int m) { return ((m & 3) ? 1 : 0) | ((m & 12) ? 2 : 0); }
 
 // The v_mfma_i32_32x32x32_i8 of one K step over the 2 x 2 tiles of 32 x 32
 // that MASK names:
@@ -384,8 +394,12 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
     static_assert(Geo::TKS * Geo::ROWB == WG_STAGE, "stage size");
     typedef typename std::conditional<ENG == ENG_F8, f32x16, i32x16>::type AccT;
     __shared__ __attribute__((aligned(16))) uint8_t lds[WG_NBUF * WG_STAGE];
-    // FP8 engine: code sums of a tile's inputs by staged-row position, P then Q
-    __shared__ int32_t f8t[ENG == ENG_F8 ? 2 * 256 : 1];
+    // Diagonal tiles split by K step (4-bit input on the int8 engine)
+    constexpr bool KSPLIT = ENG == ENG_I8 && IN_BITS == 4;
+    // FP8 engine: code sums of a tile's inputs by staged-row position, P then
+    // Q. K-split diagonal tiles: -S_i of the tile's rows i, for the waves
+    // whose blocks hold no diagonal cell of those rows.
+    __shared__ int32_t f8t[ENG == ENG_F8 ? 2 * 256 : (KSPLIT ? 128 : 1)];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -467,34 +481,58 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
     for (int k = 0; k < WG_NBUF - 1; ++k)
         if (issued < n_total) d_issue();
 
-    // This wave's part of tile w: its I inputs start at position ip, its J
-    // inputs at jp of the staged row (J half at 128), output origin (r0, c0).
-    // Off the diagonal (kind 0) each wave takes a 64 x 64 quarter. A diagonal
-    // tile (J = I, only the I half is copied) has 10 lower-triangle blocks of
-    // 32 x 32: waves 0 and 1 take the diagonal quarters without their upper
-    // block (kind 1, 3 blocks each), waves 2 and 3 the blocks of rows 64..127
-    // in columns 0..31 and 32..63 (kind 2, 2 blocks each).
-    auto role = [&](const WgItem &w, int &ip, int &jp, int &r0, int &c0, int &kind) {
+    // This wave's part of a tile: its 32-input I blocks x = 0, 1 start at
+    // staged-row positions ipos[x] (tile rows ipos[x]), its J blocks y at
+    // jpos[y] (the J half starts at 128; tile columns jpos[y] - 128, or
+    // jpos[y] on a diagonal tile, where J = I and only the I half is
+    // copied). Its MFMA blocks are (x, y), bit x + 2 y of a mask.
+    //   kind 0, off the diagonal: a 64 x 64 quarter (4 blocks).
+    // A diagonal tile has 10 lower-triangle blocks of 32 x 32 (tile blocks
+    // (a, b), b <= a).
+    //   kinds 1, 2 (FP8 engine, 8-bit input): waves 0, 1 take the diagonal
+    //   quarters without their upper block (3 blocks each), waves 2, 3 the
+    //   blocks of rows 64..127 in columns 0..31 and 32..63 (2 blocks each).
+    //   kinds 3, 4 (4-bit input on the int8 engine): 5 half blocks each, a
+    //   half block being one of the two K steps of every stage. Tile blocks
+    //   (0, 0) and (2, 1) are split: waves 0, 1 (kind 3) multiply their
+    //   block (1, 1) in the first K step only, waves 2, 3 (kind 4) their
+    //   block (0, 0) in the second K step only; the halves meet at the flush.
+    //     wave 0: I blocks (1, 2), J blocks (0, 1): (1,0) (1,1), half (2,1)
+    //     wave 1: I blocks (2, 0), J blocks (2, 0): (2,2) (2,0), half (0,0)
+    //     wave 2: I blocks (0, 3), J blocks (0, 2): (3,0) (3,2), half (0,0)
+    //     wave 3: I blocks (2, 3), J blocks (1, 3): (3,1) (3,3), half (2,1)
+    struct Role {
+        int ipos[2], jpos[2], kind;
+    };
+    auto role = [&](const WgItem &w) {
         const int bi = (int)(w.ij & 0xFFFFu), bj = (int)(w.ij >> 16);
-        const int I0 = 128 * bi, J0 = 128 * bj;
+        Role r;
         if (bi != bj) {
             const int wr = wave >> 1, wc = wave & 1;
-            ip = 64 * wr;
-            jp = 128 + 64 * wc;
-            r0 = I0 + 64 * wr;
-            c0 = J0 + 64 * wc;
-            kind = 0;
+            r.ipos[0] = 64 * wr;
+            r.jpos[0] = 128 + 64 * wc;
+            r.ipos[1] = r.ipos[0] + 32;
+            r.jpos[1] = r.jpos[0] + 32;
+            r.kind = 0;
+        } else if constexpr (KSPLIT) {
+            // tile blocks of the table above, one nibble per wave
+            r.ipos[0] = 32 * ((0x2021 >> (4 * wave)) & 3);
+            r.ipos[1] = 32 * ((0x3302 >> (4 * wave)) & 3);
+            r.jpos[0] = 32 * ((0x1020 >> (4 * wave)) & 3);
+            r.jpos[1] = 32 * ((0x3201 >> (4 * wave)) & 3);
+            r.kind = wave < 2 ? 3 : 4;
         } else if (wave < 2) {
-            ip = jp = 64 * wave;
-            r0 = c0 = I0 + 64 * wave;
-            kind = 1;
+            r.ipos[0] = r.jpos[0] = 64 * wave;
+            r.ipos[1] = r.jpos[1] = 64 * wave + 32;
+            r.kind = 1;
         } else {
-            ip = 64;
-            jp = 32 * (wave - 2);
-            r0 = I0 + 64;
-            c0 = I0 + jp;
-            kind = 2;
+            r.ipos[0] = 64;
+            r.ipos[1] = 96;
+            r.jpos[0] = 32 * (wave - 2);
+            r.jpos[1] = r.jpos[0] + 32;
+            r.kind = 2;
         }
+        return r;
     };
 
     // ---- read cursor: the stage whose fragments are read next, and the
@@ -510,13 +548,12 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
         const WgSub &sb = a.subs[w.cs >> 24];
         r_tcount = sb.t_count;
         r_nstage = (sb.t_count + TKS - 1) / TKS;
-        int ip, jp, r0, c0, kind;
-        role(w, ip, jp, r0, c0, kind);
+        const Role ro = role(w);
 #pragma unroll
         for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
             for (int blk = 0; blk < 2; ++blk) {
-                const int pos = (sd == 0 ? ip : jp) + 32 * blk + 16 * (G & 1);
+                const int pos = (sd == 0 ? ro.ipos[blk] : ro.jpos[blk]) + 16 * (G & 1);
                 if constexpr (IN_BITS == 4) {
                     const int m = (lane >> 1) & 7, h = lane & 1;
                     const int tau = 16 * (G >> 1) + m;
@@ -614,8 +651,9 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
         const WgSub &sb = a.subs[w.cs >> 24];
         const int f = (int)(w.cs & 0xFFFFFFu);
         const int nst = (sb.t_count + TKS - 1) / TKS;
-        int ip, jp, r0, c0, kind;
-        role(w, ip, jp, r0, c0, kind);
+        const Role ro = role(w);
+        const int kind = ro.kind;
+        const int ip = ro.ipos[0], jp = ro.jpos[0]; // first blocks (kinds 0..2: the second is 32 on)
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -630,22 +668,23 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
         // 0..63 and 64..127 (their I block 0 and J block 1), waves 2, 3 none
         const int sx = kind == 0 ? (wave & 1) : (wave < 2 ? 0 : -1);
         const int sy = kind == 0 ? (wave >> 1) : (wave < 2 ? 1 : -1);
-        // The stage loop of one role kind (MASK: its blocks). The stage's
-        // fragments were read by the previous step (RA). Once its last K step
-        // is unpacked RA is free, so the next stage is published and read into
-        // RA between the first wg_split() blocks of that K step's MFMAs and
-        // the rest: the MFMAs before the barrier cover its wait, those after
-        // cover the reads' latency. A diagonal quarter sums no S_i: its own
-        // diagonal holds them.
-        auto stages = [&](auto mask_c) {
-            constexpr int MASK = decltype(mask_c)::value;
-            constexpr int NY = (MASK & 0xC) ? 2 : 1;
-            constexpr bool SUMS = FUSE && MASK != 0xB;
+        // The stage loop of one role kind (M0, M1: its blocks in the first and
+        // the second K step of a stage; one K step for 8-bit input, M0 = M1).
+        // The stage's fragments were read by the previous step (RA). Once its
+        // last K step is unpacked RA is free, so the next stage is published
+        // and read into RA between the first wg_split() blocks of that K
+        // step's MFMAs and the rest: the MFMAs before the barrier cover its
+        // wait, those after cover the reads' latency. SUMS_C: the role sums
+        // S_i of its rows (the other roles find them on a diagonal cell).
+        auto stages = [&](auto m0_c, auto m1_c, auto sums_c) {
+            constexpr int M0 = decltype(m0_c)::value, M1 = decltype(m1_c)::value;
+            constexpr bool SUMS = FUSE && decltype(sums_c)::value;
+            static_assert(IN_BITS == 4 || M0 == M1, "one K step per stage");
             for (int k = 0; k < nst; ++k, ++s) {
                 if (issued < n_total) d_issue();
                 const bool more = s + 1 < n_total;
                 if constexpr (ENG == ENG_F8) {
-                    wg_f8_stage<MASK>(RA, accR, accI, sm, sx, sy);
+                    wg_f8_stage<M0>(RA, accR, accI, sm, sx, sy);
                     // the next stage's reads stay behind this stage's MFMAs
                     // (hoisted above them they would hold RA live beside the
                     // codes)
@@ -659,13 +698,19 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
                         read_frags_k(s % WG_NBUF, RA, std::integral_constant<int, 1>{},
                                      std::integral_constant<int, 2>{});
                     if constexpr (IN_BITS == 4) {
-                        wg_unpack<SUMS, NY>(RA, 0, O0, S);
-                        wg_mfma<MASK>(O0, accR, accI);
-                        wg_unpack<SUMS, NY>(RA, 1, O0, S);
+                        wg_unpack<SUMS, wg_imask(M0), wg_jmask(M0)>(RA, 0, O0, S);
+                        wg_mfma<M0>(O0, accR, accI);
+                        wg_unpack<SUMS, wg_imask(M1), wg_jmask(M1)>(RA, 1, O0, S);
                     } else {
-                        wg8_unpack<SUMS, NY>(RA, O0, S);
+                        wg8_unpack<SUMS, (M1 & 0xC) ? 2 : 1>(RA, O0, S);
                     }
-                    wg_mfma_blocks<0, wg_split<IN_BITS>(), MASK>(O0, accR, accI);
+                    wg_mfma_blocks<0, wg_split<IN_BITS>(), M1>(O0, accR, accI);
+                    // Every fragment read of this stage has returned by now
+                    // (the barrier below waits for them anyway). A wait the
+                    // compiler sees keeps it from making the blocks after the
+                    // barrier wait for the next stage's reads where the paths
+                    // with and without them join.
+                    __builtin_amdgcn_s_waitcnt(0xC07F); // lgkmcnt(0)
                     if (more) {
                         prep_stage(s + 1);
                         if constexpr (SPLIT_READS)
@@ -674,41 +719,110 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
                         else
                             read_frags((s + 1) % WG_NBUF, RA);
                     }
-                    wg_mfma_blocks<wg_split<IN_BITS>(), 4, MASK>(O0, accR, accI);
+                    wg_mfma_blocks<wg_split<IN_BITS>(), 4, M1>(O0, accR, accI);
                 }
                 if (more) r_advance();
             }
         };
+        using std::integral_constant;
+        using std::bool_constant;
         if constexpr (ENG == ENG_F8) {
             // one stage loop for every role (a role's blocks outside its mask
             // are computed but never written): a single copy of the FP8 loop
             // leaves its register allocation room
-            stages(std::integral_constant<int, 0xF>{});
+            stages(integral_constant<int, 0xF>{}, integral_constant<int, 0xF>{}, bool_constant<false>{});
+        } else if (kind == 0) {
+            stages(integral_constant<int, 0xF>{}, integral_constant<int, 0xF>{}, bool_constant<true>{});
+        } else if constexpr (KSPLIT) {
+            // split block in slot (1, 1), first K step / in slot (0, 0), second K step
+            if (kind == 3)
+                stages(integral_constant<int, 0xD>{}, integral_constant<int, 0x5>{}, bool_constant<false>{});
+            else
+                stages(integral_constant<int, 0xA>{}, integral_constant<int, 0xB>{}, bool_constant<false>{});
+        } else if (kind == 1) {
+            stages(integral_constant<int, 0xB>{}, integral_constant<int, 0xB>{}, bool_constant<false>{});
         } else {
-            if (kind == 0) stages(std::integral_constant<int, 0xF>{});
-            else if (kind == 1) stages(std::integral_constant<int, 0xB>{});
-            else stages(std::integral_constant<int, 0x3>{});
+            stages(integral_constant<int, 0x3>{}, integral_constant<int, 0x3>{}, bool_constant<true>{});
         }
 
         // ---- flush. 32 x 32 MFMA result: lane l holds column l % 32 of rows
         // 8 (r / 4) + 4 (l / 32) + r % 4. Buffer loads / stores relative to
-        // row r0: elements above the diagonal, past N, or in a block the wave
-        // does not own get an out-of-range offset (loads read 0, stores are
-        // dropped), no branches. S: lanes l and l + 32 hold halves of the row
-        // sum of row l % 32 of I block x; the int8 engines add it to Im. A
-        // diagonal quarter takes S_i from its own diagonal cell instead (Im V_ii
-        // = 0, so the raw diagonal word is -S_i).
+        // the tile's first row: elements above the diagonal, past N, or in a
+        // block the wave does not own get an out-of-range offset (loads read
+        // 0, stores are dropped), no branches. S: lanes l and l + 32 hold
+        // halves of the row sum of row l % 32 of I block x; the int8 engines
+        // add it to Im. Roles without sums take S_i from a diagonal cell
+        // (Im V_ii = 0, so the raw diagonal word is -S_i): their own, or one
+        // another wave left in f8t.
         const int N = sb.n_inputs;
-        const int ny = kind == 2 ? 1 : 2; // J blocks the wave owns
+        const int bi = (int)(w.ij & 0xFFFFu), bj = (int)(w.ij >> 16);
+        const int I0 = 128 * bi, J0 = 128 * bj;
+        const int cofs = bi == bj ? 0 : 128; // J positions -> tile columns
+        // blocks (bit x + 2 y) this wave writes
+        const int own = kind == 2 ? 0x3 : kind == 3 ? 0xD : kind == 4 ? 0xA : 0xF;
+        // per I block x, where S_i comes from: -1 the wave's sums (or no
+        // rows), 0 / 1 the diagonal cell of its block (x, 0) / (x, 1), 2 f8t
+        const int sdy0 = kind == 1 ? 0 : kind == 3 ? (wave == 0 ? 1 : 0) : -1;
+        const int sdy1 = kind == 1 ? 1 : kind == 3 ? (wave == 0 ? 2 : 1) : kind == 4 ? (wave == 2 ? 2 : 1) : -1;
         // lane-derived flush offsets from an opaque copy of the lane index, so
         // that they are not hoisted out of the tile loop (and kept live in
         // registers across the stage loop)
         int fl = lane;
         asm volatile("" : "+v"(fl));
         const int lh = fl >> 5, lc = fl & 31;
+        // the accumulator word of diagonal cell (lc, lc) of a block, in the
+        // lane that holds it (lane half (lc / 4) % 2, register
+        // 4 (lc / 8) + lc % 4), 0 in the other lane of the pair
+        auto diag_word = [&](const AccT &v) {
+            const int ri = 4 * (lc >> 3) + (lc & 3);
+            int32_t d = 0;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) d = r == ri ? (int32_t)acc_word<IN_BITS>(v[r]) : d;
+            return ((lc >> 2) & 1) == lh ? d : 0;
+        };
+        if constexpr (KSPLIT) {
+            if (kind >= 3) {
+                // Split blocks: waves 2, 3 hand their half of slot (0, 0) to
+                // waves 1, 0 (slot (1, 1)) through the LDS stage of the
+                // tile's last stage (every wave is done with it; its next
+                // copy is issued after the flush), 8 KB each. Waves 1 and 3
+                // leave -S_i of tile rows 64..127 (their diagonal cells of
+                // tile blocks (2, 2) and (3, 3)) in f8t.
+                uint8_t *mb = lds + ((s - 1) % WG_NBUF) * WG_STAGE;
+                asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+                if (kind == 4) {
+                    u32x4 *dst = (u32x4 *)(mb + (3 - wave) * 8192) + lane;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        dst[64 * c] = u32x4{(uint32_t)accR[0][0][4 * c], (uint32_t)accR[0][0][4 * c + 1],
+                                            (uint32_t)accR[0][0][4 * c + 2], (uint32_t)accR[0][0][4 * c + 3]};
+                        dst[64 * (4 + c)] = u32x4{(uint32_t)accI[0][0][4 * c], (uint32_t)accI[0][0][4 * c + 1],
+                                                  (uint32_t)accI[0][0][4 * c + 2], (uint32_t)accI[0][0][4 * c + 3]};
+                    }
+                }
+                if (FUSE && (wave & 1)) {
+                    const int x = wave == 1 ? 0 : 1;
+                    const int32_t dv = diag_word(wave == 1 ? accI[0][0] : accI[1][1]);
+                    if (((lc >> 2) & 1) == lh) f8t[ro.ipos[x] + lc] = dv;
+                }
+                asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+                if (kind == 3) {
+                    const u32x4 *src = (const u32x4 *)(mb + wave * 8192) + lane;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const u32x4 pr = src[64 * c], pi = src[64 * (4 + c)];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            accR[1][1][4 * c + e] += (int32_t)pr[e];
+                            accI[1][1][4 * c + e] += (int32_t)pi[e];
+                        }
+                    }
+                }
+            }
+        }
         const int64_t tri = (int64_t)N * (N + 1) / 2;
-        const int r1 = r0 + 64 < N ? r0 + 64 : (r0 < N ? N : r0);
-        const int64_t rb0 = (int64_t)r0 * (r0 + 1) / 2;
+        const int r1 = I0 + 128 < N ? I0 + 128 : N;
+        const int64_t rb0 = (int64_t)I0 * (I0 + 1) / 2;
         const int64_t rb1 = (int64_t)r1 * (r1 + 1) / 2;
         const size_t cell0 = (size_t)f * (size_t)tri + (size_t)rb0;
         const int nbytes = (int)((rb1 - rb0) * 8);
@@ -724,12 +838,25 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
 #pragma unroll
             for (int x = 0; x < 2; ++x) {
                 if (ENG == ENG_I8) S[x] += __shfl_xor(S[x], 32);
-                const int i = r0 + 32 * x + lc;
+                const int i = I0 + ro.ipos[x] + lc;
                 const uint32_t doff = (i < N) ? (uint32_t)((int64_t)i * (i + 1) / 2 + i - rb0) * 8u : OOR;
                 const u32x2 dg = add ? __builtin_amdgcn_raw_buffer_load_b64(srs, (int)doff, 0, 0)
                                      : u32x2{0u, 0u};
                 S[x] -= (int32_t)dg.y;
+                if constexpr (ENG == ENG_I8) {
+                    const int sdy = x == 0 ? sdy0 : sdy1;
+                    if (sdy == 0 || sdy == 1) {
+                        const int32_t dv = diag_word(sdy == 0 ? accI[x][0] : accI[x][1]);
+                        S[x] -= dv + __shfl_xor(dv, 32);
+                    } else if (KSPLIT && sdy == 2) {
+                        S[x] -= f8t[ro.ipos[x] + lc];
+                    }
+                }
             }
+        }
+        if constexpr (KSPLIT) {
+            // the merge area is free again once every wave has read it
+            if (kind >= 3) asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
         }
         // FP8 engine: the offset correction, per row (lanes l and l + 32 hold
         // halves of row l % 32's sums; the row's value is fetched by its
@@ -776,17 +903,15 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int rr = 8 * q + 4 * lh + e;
-                    const int i = r0 + 32 * x + rr;
+                    const int i = I0 + ro.ipos[x] + rr;
                     const int rel = (int)((int64_t)i * (i + 1) / 2 - rb0);
                     sv[e] = FUSE ? __shfl(S[x], rr) : 0;
                     cr[e] = ENG == ENG_F8 ? __shfl(fr[x], rr) : 0;
                     ci[e] = ENG == ENG_F8 ? __shfl(fi[x], rr) : 0;
-                    if (FUSE && ENG == ENG_I8 && kind == 1)
-                        sv[e] -= (int32_t)acc_word<IN_BITS>(__shfl(accI[x][x][4 * q + e], rr + 32 * lh));
 #pragma unroll
                     for (int y = 0; y < 2; ++y) {
-                        const int j = c0 + 32 * y + lc;
-                        off[e][y] = (y < ny && i < N && j <= i) ? (uint32_t)(rel + j) * 8u : OOR;
+                        const int j = J0 + ro.jpos[y] - cofs + lc;
+                        off[e][y] = (((own >> (x + 2 * y)) & 1) && i < N && j <= i) ? (uint32_t)(rel + j) * 8u : OOR;
                     }
                 }
                 u32x2 old[4][2];

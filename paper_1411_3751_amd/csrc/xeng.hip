@@ -277,8 +277,9 @@ void build_schedule(WavePlan &p, const std::vector<Sub> &subs, int n_cu, int wg_
                     it.w.cs = (uint32_t)f | ((uint32_t)k << 24);
                     it.w.ij = (uint32_t)bi | ((uint32_t)bj << 16);
                     // a stage loop per stage (the busiest wave of a diagonal
-                    // tile has 3 MFMA tiles, off the diagonal 4), plus a
-                    // per-tile flush
+                    // tile has 2.5 or 3 MFMA tiles, off the diagonal 4, and
+                    // the loop's other work is the same; 0.66 timed the same
+                    // as 0.75 with 2.5), plus a per-tile flush
                     it.cost = per_stage * (bi == bj ? 0.75 : 1.0) + 2.0;
                     all.push_back(it);
                 }
