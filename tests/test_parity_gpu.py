@@ -247,6 +247,30 @@ def test_every_kernel_family(torch_cuda, oracle_lib, kernel, N, F, T):
         assert np.array_equal(got, oracle_lib.narrow(wb))
 
 
+@pytest.mark.parametrize("N,F,T", [(384, 300, 200), (256, 600, 64), (128, 1500, 97), (192, 300, 1100)])
+def test_diagonal_tiles_many_per_workgroup(torch_cuda, oracle_lib, N, F, T):
+    # 4-bit input, persistent kernel: a diagonal tile's blocks are split by K
+    # step between waves and the halves meet through LDS at the flush. With
+    # many channels every workgroup flushes many diagonal tiles in a row (the
+    # hand-over slot and the S_i table are reused); whole and ragged last
+    # stages; raw sums (correlate + dump) and exact ones (correlate-and-dump)
+    from paper_1411_3751_amd import Correlator
+    torch = torch_cuda
+    print("case diagonal K split N=%d F=%d T=%d" % (N, F, T), flush=True)
+    rng = np.random.default_rng(N * 7 + F + T)
+    s = rand_stream(rng, T, F, N, 4)
+    chans = sorted(set([0, 1, F // 2, F - 2, F - 1] + rng.choice(F, 12, replace=False).tolist()))
+    want = oracle_lib.narrow(oracle_lib.correlate(s, 4, chans=chans))
+    d = torch.from_numpy(s).cuda()
+    with Correlator([dict(n_inputs=N, n_chans=F, n_time=T)]) as c:
+        assert c.plan()["subarrays"][0]["kernel"] == "persistent_workgroup"
+        c.correlate([d])
+        raw = c.dump()[0][chans].cpu().numpy()
+        fused = c.correlate_dump([d])[0][chans].cpu().numpy()
+    assert np.array_equal(raw, want)
+    assert np.array_equal(fused, want)
+
+
 @pytest.mark.parametrize("N,F,T", [(64, 5, 100), (64, 1030, 513), (64, 2, 70000), (32, 3, 256),
                                    (16, 7, 1), (48, 4, 1000), (64, 600, 4096)])
 def test_small_n_kernel(torch_cuda, oracle_lib, N, F, T):
