@@ -494,9 +494,10 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
     //   blocks of rows 64..127 in columns 0..31 and 32..63 (2 blocks each).
     //   kinds 3, 4 (4-bit input on the int8 engine): 5 half blocks each, a
     //   half block being one of the two K steps of every stage. Tile blocks
-    //   (0, 0) and (2, 1) are split: waves 0, 1 (kind 3) multiply their
-    //   block (1, 1) in the first K step only, waves 2, 3 (kind 4) their
-    //   block (0, 0) in the second K step only; the halves meet at the flush.
+    //   (0, 0) and (2, 1) are split: waves 0, 1 (kind 3) multiply their half
+    //   (accumulator slot (x, y) = (1, 1)) in the first K step of every
+    //   stage, waves 2, 3 (kind 4) theirs (slot (0, 0)) in the second; the
+    //   halves meet at the flush.
     //     wave 0: I blocks (1, 2), J blocks (0, 1): (1,0) (1,1), half (2,1)
     //     wave 1: I blocks (2, 0), J blocks (2, 0): (2,2) (2,0), half (0,0)
     //     wave 2: I blocks (0, 3), J blocks (0, 2): (3,0) (3,2), half (0,0)
