@@ -24,10 +24,17 @@ struct EvPair {
     }
 };
 
-// Mean milliseconds of `reps` runs of fn (after one untimed run); every run
-// starts from a logically zero accumulator, like a step after a dump.
+// Milliseconds per run of fn: after one untimed run, untimed batches of
+// `reps` runs until about settle_ms of work has run, then the median of
+// three timed batches of `reps` runs. Under sustained MFMA load the chip is
+// power-limited: its clock falls within milliseconds and again over a few
+// hundred, so a candidate timed on a cooler chip, or one whose extra memory
+// traffic costs clock only once the limit holds, would be favoured. Every
+// run starts from a logically zero accumulator, like a step after a dump.
+constexpr float TUNE_SETTLE_MS = 30.f;        // kernel family of one subarray
+constexpr float TUNE_SETTLE_STEP_MS = 60.f;   // schedules of whole steps
 template <class Fn>
-int time_runs(xeng_ctx *ctx, int reps, Fn fn, float &ms)
+int time_runs(xeng_ctx *ctx, int reps, Fn fn, float &ms, float settle_ms = TUNE_SETTLE_MS)
 {
     EvPair e;
     HIP_TRY(hipEventCreate(&e.a));
@@ -35,19 +42,35 @@ int time_runs(xeng_ctx *ctx, int reps, Fn fn, float &ms)
     auto zero_state = [&]() {
         for (Sub &s : ctx->subs) s.acc_zero = true;
     };
+    auto batch = [&](float &t) -> int {
+        HIP_TRY(hipEventRecord(e.a, ctx->stream));
+        for (int r = 0; r < reps; ++r) {
+            zero_state();
+            const int rc = fn();
+            if (rc) return rc;
+        }
+        HIP_TRY(hipEventRecord(e.b, ctx->stream));
+        HIP_TRY(hipEventSynchronize(e.b));
+        HIP_TRY(hipEventElapsedTime(&t, e.a, e.b));
+        return XENG_OK;
+    };
     zero_state();
     int rc = fn();
     if (rc) return rc;
-    HIP_TRY(hipEventRecord(e.a, ctx->stream));
-    for (int r = 0; r < reps; ++r) {
-        zero_state();
-        rc = fn();
+    float t[3] = {0.f, 0.f, 0.f};
+    rc = batch(t[0]);
+    if (rc) return rc;
+    const int settle = t[0] > 0.f ? std::min(1000, (int)(settle_ms / t[0])) : 0;
+    for (int q = 0; q < settle; ++q) {
+        rc = batch(t[1]);
         if (rc) return rc;
     }
-    HIP_TRY(hipEventRecord(e.b, ctx->stream));
-    HIP_TRY(hipEventSynchronize(e.b));
-    HIP_TRY(hipEventElapsedTime(&ms, e.a, e.b));
-    ms /= (float)reps;
+    for (int q = 0; q < 3; ++q) {
+        rc = batch(t[q]);
+        if (rc) return rc;
+    }
+    std::sort(t, t + 3);
+    ms = t[1] / (float)reps;
     return XENG_OK;
 }
 
@@ -94,6 +117,24 @@ int launch_all(xeng_ctx *ctx, const void *const *d_samples)
             int rc = launch_regs(ctx->subs[k], d_samples[k], ctx->stream);
             if (rc) return rc;
         }
+    return XENG_OK;
+}
+
+// The launches of a correlate-and-dump into out (the persistent kernels
+// write their last segment straight to out, the others are dumped)
+int launch_fused(xeng_ctx *ctx, const void *const *d_samples, void *const *out)
+{
+    for (WavePlan &p : ctx->plans) {
+        int rc = launch_wave(ctx, p, d_samples, out);
+        if (rc) return rc;
+    }
+    for (size_t k = 0; k < ctx->subs.size(); ++k) {
+        const Sub &s = ctx->subs[k];
+        if (s.wave) continue;
+        int rc = launch_regs(ctx->subs[k], d_samples[k], ctx->stream);
+        if (!rc) rc = dump_device(s, (uint32_t *)out[k], ctx->stream);
+        if (rc) return rc;
+    }
     return XENG_OK;
 }
 
@@ -158,22 +199,62 @@ int xeng_autotune(xeng_ctx *ctx, const void *const *d_samples, int reps)
     std::vector<SubChoice> alone;
     for (const Sub &s : ctx->subs) alone.push_back(SubChoice{fam_of(s), s.wt});
     // (2) schedule of the batched persistent launch, all subarrays together:
-    // whole steps under each schedule option
+    // whole steps under each schedule option. A step is timed both as a
+    // correlate (the launches that integrate) and as a correlate-and-dump
+    // into scratch outputs (the last launch writes the exact output, and
+    // its flush differs), and an option's time is the sum: the two kinds
+    // of step can favour different schedules.
+    std::vector<DevBuf> scratch_out;
+    std::vector<void *> outs;
+    for (const Sub &s : ctx->subs) {
+        void *p = nullptr;
+        const size_t bytes = (size_t)s.tri * (size_t)s.cfg.n_chans * 8;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            scratch_out.clear();
+            outs.clear();
+            break;
+        }
+        scratch_out.push_back(DevBuf(p, DevFree()));
+        outs.push_back(p);
+    }
+    auto time_step = [&](float &ms) -> int {
+        int rc = time_runs(ctx, reps, [&]() { return launch_all(ctx, d_samples); }, ms,
+                           TUNE_SETTLE_STEP_MS);
+        if (rc || outs.empty()) return rc;
+        float ms_fused = 0.f;
+        rc = time_runs(ctx, reps, [&]() { return launch_fused(ctx, d_samples, outs.data()); },
+                       ms_fused, TUNE_SETTLE_STEP_MS);
+        ms += ms_fused;
+        return rc;
+    };
+    // (each option timed in a forward and a reverse pass over the options,
+    // its time the mean of the two, so a drift of the clock over the passes
+    // favours none of them)
     auto tune_schedule = [&](float &best, int &bw, int &bo) -> int {
         const int opts[4][2] = {{2, 0}, {2, 1}, {1, 0}, {1, 1}};
         bool any_wave = false;
         for (const Sub &s : ctx->subs) any_wave |= s.wave;
-        for (int q = 0; q < (any_wave ? 4 : 1); ++q) {
-            ctx->wg_per_cu = opts[q][0];
-            ctx->order = opts[q][1];
-            int rc = replan(ctx);
-            if (rc) return rc;
-            float ms = 0.f;
-            rc = time_runs(ctx, reps, [&]() { return launch_all(ctx, d_samples); }, ms);
-            if (rc) return rc;
+        const int n_opt = any_wave ? 4 : 1;
+        float sum[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int pass = 0; pass < 2; ++pass)
+            for (int i = 0; i < n_opt; ++i) {
+                const int q = pass == 0 ? i : n_opt - 1 - i;
+                ctx->wg_per_cu = opts[q][0];
+                ctx->order = opts[q][1];
+                int rc = replan(ctx);
+                if (rc) return rc;
+                float ms = 0.f;
+                rc = time_step(ms);
+                if (rc) return rc;
+                sum[q] += ms;
+            }
+        for (int q = 0; q < n_opt; ++q) {
+            const float ms = sum[q] / 2.f;
             tune_note(ctx, "{\"step\": \"schedule\", \"workgroups_per_cu\": %d, \"order\": %d, "
-                           "\"ms\": %.4f}",
-                      opts[q][0], opts[q][1], ms);
+                           "\"ms\": %.4f, \"timed\": \"%s\"}",
+                      opts[q][0], opts[q][1], ms,
+                      outs.empty() ? "correlate" : "correlate + correlate_dump");
             if (q == 0 || ms < best) {
                 best = ms;
                 bw = opts[q][0];
@@ -221,7 +302,7 @@ int xeng_autotune(xeng_ctx *ctx, const void *const *d_samples, int reps)
                 rc = replan(ctx);
                 if (rc) return rc;
                 float ms = 0.f;
-                rc = time_runs(ctx, reps, [&]() { return launch_all(ctx, d_samples); }, ms);
+                rc = time_step(ms);
                 if (rc) return rc;
                 if (ms < best) best = ms;
                 else set_choice(s, fam_now, wt_now);
