@@ -223,17 +223,21 @@ int xeng_dump_fast_autos(xeng_ctx *ctx, void *const *out, int out_is_device, int
  * every kernel family that can run each subarray (XENG_KERNEL_*: the
  * persistent kernel with 128 x 128 tiles, the wave-private kernels, the
  * small-N kernel, the register-staging kernel with 32, 64 or 128-input
- * tiles), each alone, `reps` runs each, and keep the fastest; then time the
- * batched launch's schedule options (1 or 2 workgroups per CU, tiles in
- * locality order or costliest first) and keep the fastest, and whole steps
- * with every subarray the persistent kernel can run moved into one launch.
+ * tiles), each alone, and keep the fastest; then time the batched launch's
+ * schedule options (1 or 2 workgroups per CU, tiles in locality order or
+ * costliest first) and keep the fastest, and whole steps with every
+ * subarray the persistent kernel can run moved into one launch. A timing is
+ * the median of three batches of `reps` runs after untimed runs that let
+ * the clock settle; a whole step is timed both as a correlate and as a
+ * correlate-and-dump (into scratch outputs the call allocates and frees;
+ * if they cannot be allocated, as a correlate only).
  * The choices are applied to ctx and remembered for this process, keyed by
  * (device architecture, n_inputs, n_chans, n_time, in_bits, engine) per
  * subarray and per list of subarrays: later contexts with the same shapes on
  * the same architecture start with them. With the environment variable
  * XENG_TUNING_FILE set, the whole cache is then written to that file (see
  * xeng_tuning_save). Any accumulated sums are discarded (the context is left
- * reset). Blocks until done. Errors: XENG_EINVAL, XENG_EHIP.
+ * reset). Blocks until done. Errors: XENG_EINVAL, XENG_EHIP, XENG_ENOMEM.
  */
 int xeng_autotune(xeng_ctx *ctx, const void *const *d_samples, int reps);
 
