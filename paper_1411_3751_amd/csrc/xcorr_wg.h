@@ -322,11 +322,12 @@ struct F8Sums {
 };
 
 // One stage (64 samples) of the FP8 engine on the 2 x 2 tiles of 32 x 32
-// that MASK names: v_mfma_scale_f32_32x32x64_f8f6f4 with scales 2^9, and the
-// code sums of the fragments used.
+// that both MASK and the wave-uniform rmask name (a J fragment no tile uses
+// is not converted): v_mfma_scale_f32_32x32x64_f8f6f4 with scales 2^9, and
+// the code sums of the fragments sx, sy.
 template <int MASK>
 __device__ __forceinline__ void wg_f8_stage(const WgRaw &R, f32x16 (&accR)[2][2], f32x16 (&accI)[2][2],
-                                            F8Sums &sm, int sx, int sy)
+                                            F8Sums &sm, int sx, int sy, int rmask)
 {
     i32x8 reI[2], imI[2];
 #pragma unroll
@@ -344,7 +345,7 @@ __device__ __forceinline__ void wg_f8_stage(const WgRaw &R, f32x16 (&accR)[2][2]
     }
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
-        if (!((MASK >> (2 * y)) & 3)) continue; // no block of this J column
+        if (!((MASK >> (2 * y)) & 3) || !((rmask >> (2 * y)) & 3)) continue; // no block of this J column
         // the negated imaginary operand replaces the plain one in the same
         // registers once the plain one's products are issued
         i32x8 reJ, imJ;
@@ -360,7 +361,7 @@ __device__ __forceinline__ void wg_f8_stage(const WgRaw &R, f32x16 (&accR)[2][2]
         }
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
-            if (!((MASK >> (x + 2 * y)) & 1)) continue;
+            if (!((MASK >> (x + 2 * y)) & 1) || !((rmask >> (x + 2 * y)) & 1)) continue;
             accR[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(reI[x], reJ, accR[x][y], 0, 0, 0,
                                                                          F8_SCALE, 0, F8_SCALE);
             accI[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(imI[x], reJ, accI[x][y], 0, 0, 0,
@@ -371,7 +372,7 @@ __device__ __forceinline__ void wg_f8_stage(const WgRaw &R, f32x16 (&accR)[2][2]
         const i32x8 niJ = imJ ^ (int32_t)0x80808080u;
 #pragma unroll
         for (int x = 0; x < 2; ++x)
-            if ((MASK >> (x + 2 * y)) & 1)
+            if (((MASK >> (x + 2 * y)) & 1) && ((rmask >> (x + 2 * y)) & 1))
                 accI[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(reI[x], niJ, accI[x][y], 0, 0,
                                                                              0, F8_SCALE, 0, F8_SCALE);
     }
@@ -667,6 +668,10 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
         // which fragments this wave sums: off the diagonal I block (wave & 1)
         // and J block (wave >> 1); on it (J = I) waves 0 and 1 sum inputs
         // 0..63 and 64..127 (their I block 0 and J block 1), waves 2, 3 none
+        // FP8 engine: the blocks of the role (kinds 0..2), skipped by
+        // wave-uniform branches in the one stage loop
+        const int f8_mask =
+            ENG == ENG_F8 ? __builtin_amdgcn_readfirstlane(kind == 1 ? 0xB : kind == 2 ? 0x3 : 0xF) : 0xF;
         const int sx = kind == 0 ? (wave & 1) : (wave < 2 ? 0 : -1);
         const int sy = kind == 0 ? (wave >> 1) : (wave < 2 ? 1 : -1);
         // The stage loop of one role kind (M0, M1: its blocks in the first and
@@ -685,7 +690,7 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
                 if (issued < n_total) d_issue();
                 const bool more = s + 1 < n_total;
                 if constexpr (ENG == ENG_F8) {
-                    wg_f8_stage<M0>(RA, accR, accI, sm, sx, sy);
+                    wg_f8_stage<M0>(RA, accR, accI, sm, sx, sy, f8_mask);
                     // the next stage's reads stay behind this stage's MFMAs
                     // (hoisted above them they would hold RA live beside the
                     // codes)
@@ -728,9 +733,9 @@ __global__ __launch_bounds__(WG_THREADS, 2) void xcorr_wg_kernel(WgArgs a)
         using std::integral_constant;
         using std::bool_constant;
         if constexpr (ENG == ENG_F8) {
-            // one stage loop for every role (a role's blocks outside its mask
-            // are computed but never written): a single copy of the FP8 loop
-            // leaves its register allocation room
+            // one stage loop for every role, the role's blocks chosen at run
+            // time (f8_mask): a single copy of the FP8 loop leaves its
+            // register allocation room
             stages(integral_constant<int, 0xF>{}, integral_constant<int, 0xF>{}, bool_constant<false>{});
         } else if (kind == 0) {
             stages(integral_constant<int, 0xF>{}, integral_constant<int, 0xF>{}, bool_constant<true>{});
